@@ -1,0 +1,138 @@
+/*
+ * exacc.h -- C ABI of the MI355X complex spin-orbital CCSD amplitude iteration.
+ *
+ * The problem is the one the paper hands to its coupled-cluster module
+ * (section "Molecular spinors: interface to DIRAC and ReSpect" and eq.
+ * Hamiltonian): an active space of nocc occupied and nvir virtual spinors,
+ * spinor energies eps (Fock matrix f = diag(eps)) and the antisymmetrised
+ * two-electron integrals <pq||rs> = (pr|qs) - (ps|qr), here given in
+ * density-fitted form (pq|rs) = sum_P B[P][p][q] B[P][r][s].
+ *
+ * One handle = one CCSD solve resident on one GPU.  Each iteration evaluates
+ * the residual of Appendix A (eq. CC_general), takes the denominator
+ * (Jacobi) step and a Pulay DIIS extrapolation (section "Coupled cluster
+ * implementation"), all on the device.  <ab||cd> is formed tile by tile from
+ * B every iteration and never stored.
+ *
+ * Conventions for every function:
+ *   - complex numbers are interleaved (re, im) pairs of double;
+ *   - spinor index p in [0, nocc+nvir): occupied first, then virtual;
+ *   - the return value is a status: 0 = EXACC_OK, > 0 informational, < 0 error;
+ *   - a pointer argument flagged "device" must be a HIP device address that is
+ *     valid for the handle's stream; otherwise it is host memory;
+ *   - calls on one handle must be serialised by the caller; distinct handles
+ *     may be driven concurrently from different host threads.
+ */
+#ifndef EXACC_H
+#define EXACC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct exacc_ccsd_s* exacc_ccsd_t;   /* opaque; owns all device memory of one solve */
+
+enum {
+  EXACC_OK = 0,
+  EXACC_NOT_CONVERGED = 1,      /* iterate: max_steps reached before tol; results readable */
+  EXACC_ERR_INVALID_ARG = -1,   /* bad sizes, null pointer, non-finite input, non-Hermitian B, no gap */
+  EXACC_ERR_NOMEM = -2,         /* memory plan exceeds hbm_budget_bytes or a device allocation failed */
+  EXACC_ERR_DEVICE = -3,        /* a HIP runtime error (text via exacc_last_error) */
+  EXACC_ERR_DIVERGED = -4,      /* energy or step norm non-finite or grew 1e6-fold; handle stays readable */
+  EXACC_ERR_UNSUPPORTED = -5    /* option value not implemented by this build */
+};
+
+enum { EXACC_FP64 = 0, EXACC_MIXED_FP32 = 1, EXACC_MIXED_BF16X3 = 2 };
+
+/* Options; the keywords are the paper's input keywords (Supporting
+ * Information, table of ExaCorr keywords) where one exists. */
+typedef struct {
+  int    precision;          /* EXACC_FP64 (default) */
+  int    diis_size;          /* Pulay subspace size, default 8; 0 = plain Jacobi steps */
+  int    max_iter;           /* .NCYCLES, default 30 */
+  double tol;                /* .TCONVERG, default 1e-9, on ||Delta||_2 over the unique amplitudes */
+  double level_shift;        /* .LSHIFT, default 0: added to every virtual energy in the denominators */
+  int    fp64_final_iters;   /* mixed precision: at least this many FP64 iterations at the end (default 3) */
+  double mixed_switch_tol;   /* mixed precision: FP64 contractions once ||Delta|| < this (default 1e-5) */
+  int    inputs_on_device;   /* 0: eps and B passed to create are host pointers; 1: device pointers */
+  void*  stream;             /* hipStream_t to enqueue on; NULL: the handle creates its own */
+  size_t hbm_budget_bytes;   /* 0 = unlimited; create fails with EXACC_ERR_NOMEM above it */
+  long   ladder_chunk_pairs; /* a<b pairs per ladder chunk (scratch size); 0 = automatic */
+  int    timing;             /* 1: record per-stage HIP-event times (exacc_ccsd_stage_times) */
+} exacc_ccsd_opts;
+
+/* Fill *o with the defaults listed above. */
+void exacc_ccsd_default_opts(exacc_ccsd_opts* o);
+
+/* Device bytes create() will allocate for this problem (the a-priori memory
+ * footprint the paper reports in "Coupled cluster implementation").
+ * opts may be NULL (defaults).  Returns 0 for invalid sizes. */
+size_t exacc_ccsd_memory_estimate(int nocc, int nvir, int naux, const exacc_ccsd_opts* opts);
+
+/* Validate the inputs, copy them to the device, build the stored integral
+ * classes (oooo, ooov, oovv, vovo and vovv packed over c<d) and set the
+ * amplitudes to zero, so that the first iterate() step gives the MP2
+ * amplitudes.
+ *   eps : [nocc+nvir] doubles, occupied first (host or device, see opts)
+ *   B   : [naux][n][n] complex, B[P][p][q] = conj(B[P][q][p]), n = nocc+nvir
+ * Both are copied; the caller may free them on return.  On any error *out is
+ * NULL and nothing stays allocated.  Errors: INVALID_ARG (nocc, nvir or naux
+ * < 1, null pointers, non-finite entries, |B - B^H| > 1e-12 max|B|,
+ * min(eps_vir) - max(eps_occ) <= 1e-8), NOMEM, DEVICE, UNSUPPORTED. */
+int exacc_ccsd_create(exacc_ccsd_t* out, int nocc, int nvir, int naux,
+                      const double* eps, const double* B, const exacc_ccsd_opts* opts);
+
+/* Run up to max_steps iterations (eq. CC_general residual, Jacobi step, DIIS);
+ * stop early once ||Delta||_2 <= tol.  Outputs (any may be NULL): steps done,
+ * ||Delta||_2 of the last step, converged flag.  Returns OK when converged,
+ * NOT_CONVERGED when max_steps ran out, DIVERGED, DEVICE. */
+int exacc_ccsd_iterate(exacc_ccsd_t h, int max_steps, int* steps_done,
+                       double* residual, int* converged);
+
+/* FP64 correlation energy of the current amplitudes,
+ * E = sum f_ia t_i^a + 1/4 sum <ij||ab> tau_ij^ab (complex). */
+int exacc_ccsd_energy(exacc_ccsd_t h, double* e_re, double* e_im);
+
+/* Copy the current amplitudes out: t1 [nocc][nvir] complex; t2
+ * [nocc][nocc][nvir][nvir] complex, full antisymmetric.  Either may be NULL.
+ * ptr_on_device selects device (1) or host (0) destinations. */
+int exacc_ccsd_get_amplitudes(exacc_ccsd_t h, double* t1, double* t2, int ptr_on_device);
+
+/* Replace the amplitudes (same layouts as get_amplitudes; t2 must be
+ * antisymmetric: only the i<j, a<b entries are read).  Clears the DIIS
+ * history.  Used for warm restarts and to evaluate the residual at given
+ * amplitudes. */
+int exacc_ccsd_set_amplitudes(exacc_ccsd_t h, const double* t1, const double* t2, int ptr_on_device);
+
+/* The residual of eq. CC_general at the current amplitudes, without updating
+ * them: s1 [nocc][nvir], s2 [nocc][nocc][nvir][nvir] (full, antisymmetric),
+ * both including the diagonal Fock part.  Either may be NULL. */
+int exacc_ccsd_residual(exacc_ccsd_t h, double* s1, double* s2, int ptr_on_device);
+
+/* Accumulated device time in ms of each stage since create (or the last
+ * reset), measured with HIP events on the handle's stream; requires
+ * opts.timing = 1.  names[k] (static strings) and ms[k] for k < *count.
+ * Pass reset = 1 to zero the counters after reading. */
+int exacc_ccsd_stage_times(exacc_ccsd_t h, const char** names, double* ms, int* count, int reset);
+
+/* Algorithmic flop count (real flops, 8 per complex multiply-add) of one
+ * iteration's particle-particle ladder: tile build 2*naux*P_v^2 plus
+ * contraction P_o*P_v^2 complex multiply-adds, P_o = nocc(nocc-1)/2,
+ * P_v = nvir(nvir-1)/2. */
+double exacc_ladder_flops(int nocc, int nvir, int naux);
+
+/* Release every device buffer of the handle.  NULL-safe. */
+int exacc_ccsd_destroy(exacc_ccsd_t h);
+
+/* Text for a status code. */
+const char* exacc_status_string(int status);
+
+/* Text of the last error raised on the calling thread (empty if none). */
+const char* exacc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXACC_H */

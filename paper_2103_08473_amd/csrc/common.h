@@ -1,0 +1,90 @@
+// Shared declarations of the exacc HIP library (device kernels + host driver).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+namespace exacc {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+struct cplx {
+  double re, im;
+};
+
+// Error raised inside the library; mapped to a status code at the C ABI.
+struct Error {
+  int status;
+  std::string msg;
+};
+
+[[noreturn]] void raise(int status, const std::string& msg);
+void hip_check(hipError_t e, const char* what, const char* file, int line);
+#define HIPCHECK(x) ::exacc::hip_check((x), #x, __FILE__, __LINE__)
+
+// ---------------------------------------------------------------------------
+// GETT: C[b](m, n) = alpha * sum_k opA(A[b](m, k)) * opB(B[b](k, n)) (+ C[b](m, n))
+// Each of m, n, k is a composite index split into (outer, inner):
+//   offset(x) = (x / x_in) * x_so + (x % x_in) * x_si      (complex elements)
+// which covers any contraction whose index groups merge into two strided
+// levels per operand (the host planner in einsum.cpp finds the split).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Gett {
+  int M, N, K, nbatch;
+  int m_in, n_in, k_in;
+  int64_t a_mo, a_mi, a_ko, a_ki, a_b;
+  int64_t b_ko, b_ki, b_no, b_ni, b_b;
+  int64_t c_mo, c_mi, c_no, c_ni, c_b;
+  int conj_a, conj_b, accumulate;
+  R alpha_re, alpha_im;
+  const R* A;  // interleaved complex
+  const R* B;
+  R* C;
+};
+
+enum GettKind { GETT_GENERIC = 0, GETT_LADDER_BUILD = 1, GETT_LADDER_CONTRACT = 2, GETT_RING = 3 };
+
+template <typename R>
+void launch_gett(const Gett<R>& g, int kind, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Bandwidth kernels (elementwise.hip).  Sizes in elements; complex arrays are
+// interleaved (re, im).  Packed pair index of (p<q) over m: p*m - p(p+1)/2 + q-p-1.
+// ---------------------------------------------------------------------------
+void k_transpose_B(const double* B, double* Bt, int64_t X, int64_t nn, hipStream_t s);
+void k_check_B(const double* B, int64_t X, int n, double* out3, double* scratch, hipStream_t s);
+void k_pack_last2(double* out, const double* in, const int* rowmap, int64_t rows, int m,
+                  int64_t in_row_stride, hipStream_t s);
+void k_unpack_tau(const double* t1, const double* t2p, double* T2, double* TAU, double* taup,
+                  int o, int v, hipStream_t s);
+void k_ring_operands(const double* T2, const double* t1, double* Tq, double* Xp, int o, int v,
+                     hipStream_t s);
+void k_expand_c(const double* Vooov, const double* Cp, double* Cf, int o, int v, hipStream_t s);
+void k_ladder_antisym(const double* Ta, double* W, int nb, int v, hipStream_t s);
+void k_assemble_t2(const double* Znp, const double* Zab, const double* Zij, const double* R,
+                   const double* Voovv_p, const double* t2p, const double* eps, int o, int v,
+                   double shift, double* xt, double* e, double* s2_full, double* partial,
+                   int nblk, hipStream_t s);
+void k_assemble_t1(const double* S1, const double* t1, const double* eps, int o, int v,
+                   double shift, double* xt, double* e, double* s1_full, double* partial,
+                   hipStream_t s);
+int assemble_t2_blocks(int64_t npairs);
+void k_reduce_sum(const double* partial, int n, int width, double* out, hipStream_t s);
+void k_dot_many(const double* const* es, int m, const double* e, int64_t len, double* partial,
+                int nblk, hipStream_t s);
+int dot_many_blocks(int64_t len);
+void k_lincomb(double* x, const double* const* xs, const cplx* c, int m, int64_t len,
+               hipStream_t s);
+void k_energy(const double* Voovv_p, const double* t2p, const double* t1, int o, int v,
+              double* partial, int nblk, hipStream_t s);
+int energy_blocks(int64_t npairs);
+void k_unpack_full(const double* t1, const double* t2p, double* t1_out, double* t2_out, int o,
+                   int v, hipStream_t s);
+void k_pack_amplitudes(const double* t1, const double* t2, double* x, int o, int v,
+                       hipStream_t s);
+
+}  // namespace exacc

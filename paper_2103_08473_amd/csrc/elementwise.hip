@@ -1,0 +1,566 @@
+// HBM-bound kernels of the CCSD iteration: packing of antisymmetric pairs,
+// tau formation, operand permutes for the ring contractions, the residual
+// assembly fused with the denominator (Jacobi) step, DIIS vector operations,
+// the energy, and fixed-order (deterministic, atomic-free) reductions.
+#include "common.h"
+
+namespace exacc {
+
+namespace {
+
+constexpr int TB = 256;
+
+struct z {
+  double x, y;
+};
+__device__ __forceinline__ z ld(const double* p, int64_t i) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  v2 t = *reinterpret_cast<const v2*>(p + 2 * i);
+  return z{t.x, t.y};
+}
+__device__ __forceinline__ void st(double* p, int64_t i, z v) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  v2 t;
+  t.x = v.x;
+  t.y = v.y;
+  *reinterpret_cast<v2*>(p + 2 * i) = t;
+}
+__device__ __forceinline__ z add(z a, z b) { return z{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ z sub(z a, z b) { return z{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ z mul(z a, z b) { return z{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ z scal(double s, z a) { return z{s * a.x, s * a.y}; }
+
+// (p, q), p < q, from the packed index x of pairs over m (row-major by p).
+__device__ __forceinline__ void pair_of(int64_t x, int m, int& p, int& q) {
+  const double tm = 2.0 * m - 1.0;
+  int a = (int)floor((tm - sqrt(tm * tm - 8.0 * (double)x)) * 0.5);
+  if (a < 0) a = 0;
+  // exact correction for rounding at row boundaries
+  while (a > 0 && (int64_t)a * m - (int64_t)a * (a + 1) / 2 > x) --a;
+  while ((int64_t)(a + 1) * m - (int64_t)(a + 1) * (a + 2) / 2 <= x) ++a;
+  p = a;
+  q = (int)(x - ((int64_t)a * m - (int64_t)a * (a + 1) / 2)) + a + 1;
+}
+__device__ __forceinline__ int64_t pidx(int p, int q, int m) {
+  return (int64_t)p * m - (int64_t)p * (p + 1) / 2 + (q - p - 1);
+}
+
+inline int nblocks(int64_t n, int cap = 65535 * 8) {
+  int64_t b = (n + TB - 1) / TB;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+// ------------------------------------------------------------------ B staging
+__global__ void transpose_B_kernel(const double* __restrict__ B, double* __restrict__ Bt, int64_t X,
+                                   int64_t nn) {
+  __shared__ double tr[32][33], ti[32][33];
+  const int64_t q0 = (int64_t)blockIdx.x * 32, P0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t P = P0 + r, q = q0 + tx;
+    if (P < X && q < nn) {
+      z v = ld(B, P * nn + q);
+      tr[r][tx] = v.x;
+      ti[r][tx] = v.y;
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t q = q0 + r, P = P0 + tx;
+    if (P < X && q < nn) st(Bt, q * X + P, z{tr[tx][r], ti[tx][r]});
+  }
+}
+
+// out3 = {max |B - B^H|, max |B|, number of non-finite entries}
+__global__ void check_B_kernel(const double* __restrict__ B, int64_t X, int n,
+                               double* __restrict__ part) {
+  double mh = 0, mb = 0, nf = 0;
+  const int64_t nn = (int64_t)n * n, tot = X * nn;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int64_t P = t / nn, r = t - P * nn;
+    const int p = (int)(r / n), q = (int)(r - (int64_t)p * n);
+    z a = ld(B, t), b = ld(B, P * nn + (int64_t)q * n + p);
+    if (!isfinite(a.x) || !isfinite(a.y)) nf += 1;
+    const double dh = fmax(fabs(a.x - b.x), fabs(a.y + b.y));
+    mh = fmax(mh, dh);
+    mb = fmax(mb, fmax(fabs(a.x), fabs(a.y)));
+  }
+  __shared__ double s[3][TB];
+  s[0][threadIdx.x] = mh;
+  s[1][threadIdx.x] = mb;
+  s[2][threadIdx.x] = nf;
+  __syncthreads();
+  for (int w = TB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s[0][threadIdx.x] = fmax(s[0][threadIdx.x], s[0][threadIdx.x + w]);
+      s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + w]);
+      s[2][threadIdx.x] += s[2][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x + 0] = s[0][0];
+    part[3 * blockIdx.x + 1] = s[1][0];
+    part[3 * blockIdx.x + 2] = s[2][0];
+  }
+}
+
+__global__ void check_B_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double a = 0, b = 0, c = 0;
+    for (int i = 0; i < nb; ++i) {
+      a = fmax(a, part[3 * i]);
+      b = fmax(b, part[3 * i + 1]);
+      c += part[3 * i + 2];
+    }
+    out[0] = a;
+    out[1] = b;
+    out[2] = c;
+  }
+}
+
+// ------------------------------------------------------------------ packing
+__global__ void pack_last2_kernel(double* __restrict__ out, const double* __restrict__ in,
+                                  const int* __restrict__ rowmap, int64_t rows, int m,
+                                  int64_t in_row_stride) {
+  const int64_t P = (int64_t)m * (m - 1) / 2, tot = rows * P;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int64_t r = t / P, x = t - r * P;
+    int a, b;
+    pair_of(x, m, a, b);
+    const int64_t rr = rowmap ? rowmap[r] : r;
+    st(out, t, ld(in, rr * in_row_stride + (int64_t)a * m + b));
+  }
+}
+
+// T2 (full), TAU (full) and packed tau from t1 and packed t2.
+__global__ void unpack_tau_kernel(const double* __restrict__ t1, const double* __restrict__ t2p,
+                                  double* __restrict__ T2, double* __restrict__ TAU,
+                                  double* __restrict__ taup, int o, int v) {
+  const int64_t vv = (int64_t)v * v, tot = (int64_t)o * o * vv, Pv = (int64_t)v * (v - 1) / 2;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int64_t ij = t / vv, ab = t - ij * vv;
+    const int i = (int)(ij / o), j = (int)(ij - (int64_t)i * o);
+    const int a = (int)(ab / v), b = (int)(ab - (int64_t)a * v);
+    z val{0, 0};
+    if (i != j && a != b) {
+      const int pi = i < j ? i : j, pj = i < j ? j : i;
+      const int pa = a < b ? a : b, pb = a < b ? b : a;
+      const double sg = ((i < j) == (a < b)) ? 1.0 : -1.0;
+      val = scal(sg, ld(t2p, pidx(pi, pj, o) * Pv + pidx(pa, pb, v)));
+    }
+    st(T2, t, val);
+    const z tt = sub(mul(ld(t1, (int64_t)i * v + a), ld(t1, (int64_t)j * v + b)),
+                     mul(ld(t1, (int64_t)j * v + a), ld(t1, (int64_t)i * v + b)));
+    const z tau = add(val, tt);
+    st(TAU, t, tau);
+    if (i < j && a < b) st(taup, pidx(i, j, o) * Pv + pidx(a, b, v), tau);
+  }
+}
+
+// Tq[b][j][k][c] = T2[j][k][c][b];  Xp[b][j][k][c] = 1/2 Tq + t1[k][b] t1[j][c]
+__global__ void ring_operands_kernel(const double* __restrict__ T2, const double* __restrict__ t1,
+                                     double* __restrict__ Tq, double* __restrict__ Xp, int o, int v) {
+  __shared__ double tr[32][33], ti[32][33];
+  const int b0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+  const int64_t jk = blockIdx.z;
+  const int j = (int)(jk / o), k = (int)(jk - (int64_t)j * o);
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int64_t vv = (int64_t)v * v, oo = (int64_t)o * o;
+  for (int r = ty; r < 32; r += 8) {
+    const int c = c0 + r, b = b0 + tx;
+    if (c < v && b < v) {
+      z x = ld(T2, jk * vv + (int64_t)c * v + b);
+      tr[r][tx] = x.x;
+      ti[r][tx] = x.y;
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int b = b0 + r, c = c0 + tx;
+    if (c < v && b < v) {
+      const z q{tr[tx][r], ti[tx][r]};
+      const int64_t off = ((int64_t)b * oo + jk) * v + c;
+      st(Tq, off, q);
+      st(Xp, off, add(scal(0.5, q), mul(ld(t1, (int64_t)k * v + b), ld(t1, (int64_t)j * v + c))));
+    }
+  }
+}
+
+// Cf[i][j][b][k] = conj(Vooov[i][j][k][b]) + sign(i,j) Cp[(min,max)][b][k]
+__global__ void expand_c_kernel(const double* __restrict__ Vooov, const double* __restrict__ Cp,
+                                double* __restrict__ Cf, int o, int v) {
+  const int64_t tot = (int64_t)o * o * v * o;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    int64_t r = t;
+    const int k = (int)(r % o);
+    r /= o;
+    const int b = (int)(r % v);
+    r /= v;
+    const int j = (int)(r % o);
+    const int i = (int)(r / o);
+    z x = ld(Vooov, (((int64_t)i * o + j) * o + k) * v + b);
+    x.y = -x.y;
+    if (i != j) {
+      const int p = i < j ? i : j, q = i < j ? j : i;
+      z c = ld(Cp, (pidx(p, q, o) * v + b) * o + k);
+      x = (i < j) ? add(x, c) : sub(x, c);
+    }
+    st(Cf, t, x);
+  }
+}
+
+// W[b'][x=(c<d)] = Ta[c][b'][d] - Ta[d][b'][c]
+__global__ void ladder_antisym_kernel(const double* __restrict__ Ta, double* __restrict__ W, int nb,
+                                      int v) {
+  const int64_t Pv = (int64_t)v * (v - 1) / 2, tot = (int64_t)nb * Pv;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int64_t bp = t / Pv, x = t - bp * Pv;
+    int c, d;
+    pair_of(x, v, c, d);
+    const z p = ld(Ta, ((int64_t)c * nb + bp) * v + d);
+    const z q = ld(Ta, ((int64_t)d * nb + bp) * v + c);
+    st(W, t, sub(p, q));
+  }
+}
+
+// Residual assembly + Jacobi step for the doubles (packed i<j, a<b).
+__global__ void assemble_t2_kernel(const double* __restrict__ Znp, const double* __restrict__ Zab,
+                                   const double* __restrict__ Zij, const double* __restrict__ R,
+                                   const double* __restrict__ Vp, const double* __restrict__ t2p,
+                                   const double* __restrict__ eps, int o, int v, double shift,
+                                   double* __restrict__ xt, double* __restrict__ e,
+                                   double* __restrict__ s2, double* __restrict__ part) {
+  const int64_t Po = (int64_t)o * (o - 1) / 2, Pv = (int64_t)v * (v - 1) / 2, tot = Po * Pv;
+  const int64_t vv = (int64_t)v * v;
+  double acc = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int64_t p = t / Pv, x = t - p * Pv;
+    int i, j, a, b;
+    pair_of(p, o, i, j);
+    pair_of(x, v, a, b);
+    const int64_t ijab = ((int64_t)i * o + j) * vv + (int64_t)a * v + b;
+    const int64_t ijba = ((int64_t)i * o + j) * vv + (int64_t)b * v + a;
+    const int64_t jiab = ((int64_t)j * o + i) * vv + (int64_t)a * v + b;
+    const int64_t jiba = ((int64_t)j * o + i) * vv + (int64_t)b * v + a;
+    z s = ld(Znp, t);
+    s = add(s, sub(ld(Zab, ijab), ld(Zab, ijba)));
+    s = add(s, sub(ld(Zij, ijab), ld(Zij, jiab)));
+    s = add(s, add(sub(ld(R, ijab), ld(R, jiab)), sub(ld(R, jiba), ld(R, ijba))));
+    z g = ld(Vp, t);
+    s.x += g.x;
+    s.y -= g.y;
+    const z tt = ld(t2p, t);
+    const double D = eps[o + a] + eps[o + b] - eps[i] - eps[j];
+    s = add(s, scal(D, tt));
+    if (s2) {
+      st(s2, ijab, s);
+      st(s2, jiba, s);
+      st(s2, ijba, scal(-1.0, s));
+      st(s2, jiab, scal(-1.0, s));
+    } else {
+      const z dl = scal(-1.0 / (D + 2.0 * shift), s);
+      st(e, t, dl);
+      st(xt, t, add(tt, dl));
+      acc += dl.x * dl.x + dl.y * dl.y;
+    }
+  }
+  __shared__ double sh[TB];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = TB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && part) part[blockIdx.x] = sh[0];
+}
+
+__global__ void assemble_t1_kernel(const double* __restrict__ S1, const double* __restrict__ t1,
+                                   const double* __restrict__ eps, int o, int v, double shift,
+                                   double* __restrict__ xt, double* __restrict__ e,
+                                   double* __restrict__ s1, double* __restrict__ part) {
+  const int64_t tot = (int64_t)o * v;
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < tot; t += TB) {
+    const int i = (int)(t / v), a = (int)(t - (int64_t)i * v);
+    const double D = eps[o + a] - eps[i];
+    const z tt = ld(t1, t);
+    const z s = add(ld(S1, t), scal(D, tt));
+    if (s1) {
+      st(s1, t, s);
+    } else {
+      const z dl = scal(-1.0 / (D + shift), s);
+      st(e, t, dl);
+      st(xt, t, add(tt, dl));
+      acc += dl.x * dl.x + dl.y * dl.y;
+    }
+  }
+  __shared__ double sh[TB];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = TB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && part) part[0] = sh[0];
+}
+
+// out[w] = sum_b partial[b*width + w], fixed order, one block.
+__global__ void reduce_sum_kernel(const double* __restrict__ partial, int n, int width,
+                                  double* __restrict__ out) {
+  __shared__ double sh[TB];
+  for (int w = 0; w < width; ++w) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < n; b += TB) acc += partial[(int64_t)b * width + w];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = TB / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[w] = sh[0];
+    __syncthreads();
+  }
+}
+
+constexpr int MAXV = 16;
+struct Ptrs {
+  const double* p[MAXV];
+};
+struct Coefs {
+  double re[MAXV], im[MAXV];
+};
+
+// partial[blk][k] = sum_i conj(es[k][i]) e[i]   (complex, k < m)
+__global__ void dot_many_kernel(Ptrs es, int m, const double* __restrict__ e, int64_t len,
+                                double* __restrict__ part) {
+  double ar[MAXV], ai[MAXV];
+#pragma unroll
+  for (int k = 0; k < MAXV; ++k) ar[k] = ai[k] = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < len; t += (int64_t)gridDim.x * TB) {
+    const z y = ld(e, t);
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      if (k < m) {
+        const z x = ld(es.p[k], t);
+        ar[k] += x.x * y.x + x.y * y.y;
+        ai[k] += x.x * y.y - x.y * y.x;
+      }
+    }
+  }
+  __shared__ double sh[TB];
+  for (int k = 0; k < m; ++k) {
+    for (int c = 0; c < 2; ++c) {
+      sh[threadIdx.x] = c ? ai[k] : ar[k];
+      __syncthreads();
+      for (int s = TB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) part[((int64_t)blockIdx.x * m + k) * 2 + c] = sh[0];
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void lincomb_kernel(double* __restrict__ x, Ptrs xs, Coefs c, int m, int64_t len) {
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < len; t += (int64_t)gridDim.x * TB) {
+    z acc{0, 0};
+    for (int k = 0; k < m; ++k) acc = add(acc, mul(z{c.re[k], c.im[k]}, ld(xs.p[k], t)));
+    st(x, t, acc);
+  }
+}
+
+// E partial = sum_{i<j,a<b} <ij||ab> (t_ij^ab + t_i^a t_j^b - t_j^a t_i^b)
+__global__ void energy_kernel(const double* __restrict__ Vp, const double* __restrict__ t2p,
+                              const double* __restrict__ t1, int o, int v,
+                              double* __restrict__ part) {
+  const int64_t Po = (int64_t)o * (o - 1) / 2, Pv = (int64_t)v * (v - 1) / 2, tot = Po * Pv;
+  double er = 0, ei = 0;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int64_t p = t / Pv, x = t - p * Pv;
+    int i, j, a, b;
+    pair_of(p, o, i, j);
+    pair_of(x, v, a, b);
+    const z tau = add(ld(t2p, t), sub(mul(ld(t1, (int64_t)i * v + a), ld(t1, (int64_t)j * v + b)),
+                                      mul(ld(t1, (int64_t)j * v + a), ld(t1, (int64_t)i * v + b))));
+    const z g = mul(ld(Vp, t), tau);
+    er += g.x;
+    ei += g.y;
+  }
+  __shared__ double sr[TB], si[TB];
+  sr[threadIdx.x] = er;
+  si[threadIdx.x] = ei;
+  __syncthreads();
+  for (int s = TB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sr[0];
+    part[2 * blockIdx.x + 1] = si[0];
+  }
+}
+
+__global__ void unpack_full_kernel(const double* __restrict__ t2p, double* __restrict__ t2, int o,
+                                   int v) {
+  const int64_t vv = (int64_t)v * v, tot = (int64_t)o * o * vv, Pv = (int64_t)v * (v - 1) / 2;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int64_t ij = t / vv, ab = t - ij * vv;
+    const int i = (int)(ij / o), j = (int)(ij - (int64_t)i * o);
+    const int a = (int)(ab / v), b = (int)(ab - (int64_t)a * v);
+    z val{0, 0};
+    if (i != j && a != b) {
+      const int pi = i < j ? i : j, pj = i < j ? j : i;
+      const int pa = a < b ? a : b, pb = a < b ? b : a;
+      const double sg = ((i < j) == (a < b)) ? 1.0 : -1.0;
+      val = scal(sg, ld(t2p, pidx(pi, pj, o) * Pv + pidx(pa, pb, v)));
+    }
+    st(t2, t, val);
+  }
+}
+
+__global__ void pack_amp_kernel(const double* __restrict__ t2, double* __restrict__ x2, int o,
+                                int v) {
+  const int64_t Po = (int64_t)o * (o - 1) / 2, Pv = (int64_t)v * (v - 1) / 2, tot = Po * Pv;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int64_t p = t / Pv, x = t - p * Pv;
+    int i, j, a, b;
+    pair_of(p, o, i, j);
+    pair_of(x, v, a, b);
+    st(x2, t, ld(t2, (((int64_t)i * o + j) * v + a) * v + b));
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+void k_transpose_B(const double* B, double* Bt, int64_t X, int64_t nn, hipStream_t s) {
+  dim3 grid((unsigned)((nn + 31) / 32), (unsigned)((X + 31) / 32)), block(32, 8);
+  hipLaunchKernelGGL(transpose_B_kernel, grid, block, 0, s, B, Bt, X, nn);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_check_B(const double* B, int64_t X, int n, double* out3, double* scratch, hipStream_t s) {
+  const int nb = 1024;
+  hipLaunchKernelGGL(check_B_kernel, dim3(nb), dim3(TB), 0, s, B, X, n, scratch);
+  HIPCHECK(hipGetLastError());
+  hipLaunchKernelGGL(check_B_final, dim3(1), dim3(64), 0, s, scratch, nb, out3);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_pack_last2(double* out, const double* in, const int* rowmap, int64_t rows, int m,
+                  int64_t in_row_stride, hipStream_t s) {
+  const int64_t tot = rows * ((int64_t)m * (m - 1) / 2);
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(pack_last2_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, out, in, rowmap, rows, m,
+                     in_row_stride);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_unpack_tau(const double* t1, const double* t2p, double* T2, double* TAU, double* taup, int o,
+                  int v, hipStream_t s) {
+  const int64_t tot = (int64_t)o * o * v * v;
+  hipLaunchKernelGGL(unpack_tau_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, t1, t2p, T2, TAU, taup, o,
+                     v);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_ring_operands(const double* T2, const double* t1, double* Tq, double* Xp, int o, int v,
+                     hipStream_t s) {
+  const int64_t oo = (int64_t)o * o;
+  if (oo > 65535) raise(-5, "nocc too large for ring operand permute");
+  dim3 grid((v + 31) / 32, (v + 31) / 32, (unsigned)oo), block(32, 8);
+  hipLaunchKernelGGL(ring_operands_kernel, grid, block, 0, s, T2, t1, Tq, Xp, o, v);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_expand_c(const double* Vooov, const double* Cp, double* Cf, int o, int v, hipStream_t s) {
+  const int64_t tot = (int64_t)o * o * o * v;
+  hipLaunchKernelGGL(expand_c_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, Vooov, Cp, Cf, o, v);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_ladder_antisym(const double* Ta, double* W, int nb, int v, hipStream_t s) {
+  const int64_t tot = (int64_t)nb * ((int64_t)v * (v - 1) / 2);
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(ladder_antisym_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, Ta, W, nb, v);
+  HIPCHECK(hipGetLastError());
+}
+
+int assemble_t2_blocks(int64_t npairs) { return nblocks(npairs, 4096); }
+int dot_many_blocks(int64_t len) { return nblocks(len, 2048); }
+int energy_blocks(int64_t npairs) { return nblocks(npairs, 2048); }
+
+void k_assemble_t2(const double* Znp, const double* Zab, const double* Zij, const double* R,
+                   const double* Voovv_p, const double* t2p, const double* eps, int o, int v,
+                   double shift, double* xt, double* e, double* s2_full, double* partial, int nblk,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(assemble_t2_kernel, dim3(nblk), dim3(TB), 0, s, Znp, Zab, Zij, R, Voovv_p, t2p,
+                     eps, o, v, shift, xt, e, s2_full, partial);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_assemble_t1(const double* S1, const double* t1, const double* eps, int o, int v, double shift,
+                   double* xt, double* e, double* s1_full, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(assemble_t1_kernel, dim3(1), dim3(TB), 0, s, S1, t1, eps, o, v, shift, xt, e,
+                     s1_full, partial);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_reduce_sum(const double* partial, int n, int width, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(TB), 0, s, partial, n, width, out);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_dot_many(const double* const* es, int m, const double* e, int64_t len, double* partial,
+                int nblk, hipStream_t s) {
+  if (m > MAXV) raise(-1, "DIIS subspace larger than 16");
+  Ptrs p{};
+  for (int k = 0; k < m; ++k) p.p[k] = es[k];
+  hipLaunchKernelGGL(dot_many_kernel, dim3(nblk), dim3(TB), 0, s, p, m, e, len, partial);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_lincomb(double* x, const double* const* xs, const cplx* c, int m, int64_t len, hipStream_t s) {
+  if (m > MAXV) raise(-1, "DIIS subspace larger than 16");
+  Ptrs p{};
+  Coefs cc{};
+  for (int k = 0; k < m; ++k) {
+    p.p[k] = xs[k];
+    cc.re[k] = c[k].re;
+    cc.im[k] = c[k].im;
+  }
+  hipLaunchKernelGGL(lincomb_kernel, dim3(nblocks(len, 8192)), dim3(TB), 0, s, x, p, cc, m, len);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_energy(const double* Voovv_p, const double* t2p, const double* t1, int o, int v,
+              double* partial, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(energy_kernel, dim3(nblk), dim3(TB), 0, s, Voovv_p, t2p, t1, o, v, partial);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_unpack_full(const double* t1, const double* t2p, double* t1_out, double* t2_out, int o, int v,
+                   hipStream_t s) {
+  (void)t1;
+  (void)t1_out;
+  const int64_t tot = (int64_t)o * o * v * v;
+  hipLaunchKernelGGL(unpack_full_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, t2p, t2_out, o, v);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_pack_amplitudes(const double* t1, const double* t2, double* x, int o, int v, hipStream_t s) {
+  (void)t1;
+  const int64_t tot = ((int64_t)o * (o - 1) / 2) * ((int64_t)v * (v - 1) / 2);
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(pack_amp_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, t2, x, o, v);
+  HIPCHECK(hipGetLastError());
+}
+
+}  // namespace exacc

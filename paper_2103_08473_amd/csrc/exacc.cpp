@@ -1,0 +1,955 @@
+// exacc C ABI: one handle per CCSD solve resident on the device.
+//
+// Per iteration (Appendix A, eq. CC_general), all on the handle's stream:
+//   tau and permuted amplitude copies -> one-body intermediates H/G ->
+//   H^{ak}_{ci} (ring intermediate) -> ring contraction -> C^{kb}_{ij} ->
+//   A^{kl}_{ij} and hole ladder -> particle ladder from density-fitting tiles ->
+//   singles residual -> residual assembly fused with the denominator step ->
+//   DIIS Gram row -> (host: small bordered solve) -> extrapolation -> energy.
+// The diagonal Fock terms (eps_a + eps_b - eps_i - eps_j) t of the residual are
+// added in the assembly kernel rather than through H and G; the sum is the same.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/exacc.h"
+#include "common.h"
+#include "einsum.h"
+
+namespace exacc {
+
+static thread_local std::string g_last_error;
+
+void raise(int status, const std::string& msg) { throw Error{status, msg}; }
+
+void hip_check(hipError_t e, const char* what, const char* file, int line) {
+  if (e == hipSuccess) return;
+  char buf[512];
+  snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+  if (e == hipErrorOutOfMemory) raise(EXACC_ERR_NOMEM, buf);
+  raise(EXACC_ERR_DEVICE, buf);
+}
+
+typedef std::complex<double> zc;
+
+static inline int64_t npair(int64_t m) { return m * (m - 1) / 2; }
+
+// ------------------------------------------------------------------ memory plan
+struct Plan {
+  int o, v, X, n;
+  int64_t Po, Pv, L, vv, oovv;
+  int64_t chunk_pairs;  // ladder W rows
+  int nslots;
+  int64_t vovv_chunk;   // b values per vovv build step (create only)
+  // complex-element counts
+  struct Item {
+    const char* name;
+    int64_t elems;
+    bool transient;
+  };
+  std::vector<Item> items;
+  size_t bytes_persistent = 0, bytes_peak = 0;
+};
+
+static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
+  Plan p;
+  p.o = o;
+  p.v = v;
+  p.X = X;
+  p.n = o + v;
+  p.Po = npair(o);
+  p.Pv = npair(v);
+  p.L = (int64_t)o * v + p.Po * p.Pv;
+  p.vv = (int64_t)v * v;
+  p.oovv = (int64_t)o * o * p.vv;
+  p.nslots = std::max(1, op.diis_size);
+  const int64_t rowbytes = std::max<int64_t>(1, p.Pv) * 16;
+  int64_t cp = op.ladder_chunk_pairs;
+  if (cp <= 0) cp = std::max<int64_t>(v, (int64_t)(8ll << 30) / rowbytes);
+  cp = std::min<int64_t>(std::max<int64_t>(cp, std::max(1, v - 1)), std::max<int64_t>(1, p.Pv));
+  p.chunk_pairs = cp;
+  const int64_t vovv_row = (int64_t)o * v * v;  // per b
+  p.vovv_chunk = std::max<int64_t>(1, std::min<int64_t>(v, (int64_t)(2ll << 30) / (16 * vovv_row)));
+  const int64_t n = p.n, oo = (int64_t)o * o;
+  auto add = [&](const char* nm, int64_t e, bool tr = false) { p.items.push_back({nm, e, tr}); };
+  add("Bt", n * n * X);
+  add("Voooo", oo * oo);
+  add("Vooov", oo * o * v);
+  add("Voovv", p.oovv);
+  add("Voovv_p", p.Po * p.Pv);
+  add("Vvovo", p.oovv);
+  add("Vvovv_p", (int64_t)v * o * p.Pv);
+  add("x", p.L);
+  add("diis", 2 * p.nslots * p.L);
+  add("T2", p.oovv);
+  add("TAU", p.oovv);
+  add("taup", p.Po * p.Pv);
+  add("Tq", p.oovv);
+  add("Xp", p.oovv);
+  add("H4", p.oovv);
+  add("R", p.oovv);
+  add("Zij", p.oovv);
+  add("Zab", p.oovv);
+  add("Znp", p.Po * p.Pv);
+  add("small", 2 * p.vv + 3 * oo + 2 * (int64_t)o * v + X + p.vv * X + oo * X + 2 * (int64_t)v * o * X +
+                   p.Po * v * o + oo * v * o + oo * oo + p.Po * p.Po);
+  add("Ta", (int64_t)v * std::max(1, v - 1) * v);
+  add("W", p.chunk_pairs * std::max<int64_t>(1, p.Pv));
+  add("Braw", n * n * X, true);
+  add("vovv_tmp", p.vovv_chunk * vovv_row, true);
+  size_t pers = 0, tr = 0;
+  for (auto& it : p.items) {
+    const size_t b = (size_t)it.elems * 16 + 256;
+    if (it.transient)
+      tr = std::max(tr, b);
+    else
+      pers += b;
+  }
+  pers += 1 << 20;  // reductions, tables, eps
+  p.bytes_persistent = pers;
+  p.bytes_peak = pers + tr + (size_t)(n * n * X) * 16;  // Braw and vovv_tmp not live together
+  return p;
+}
+
+// ------------------------------------------------------------------ handle
+struct Timer {
+  bool on = false;
+  std::vector<std::string> names;
+  std::vector<double> ms;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  int id(const char* nm) {
+    for (size_t i = 0; i < names.size(); ++i)
+      if (names[i] == nm) return (int)i;
+    names.push_back(nm);
+    ms.push_back(0.0);
+    return (int)names.size() - 1;
+  }
+  hipEvent_t ev() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      HIPCHECK(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+
+struct Handle {
+  Plan P;
+  exacc_ccsd_opts op;
+  hipStream_t s = nullptr;
+  bool own_stream = false;
+  std::vector<void*> allocs;
+  std::vector<AllocRange> ranges;  // allocs with sizes, for the planner's extent check
+  double* eps = nullptr;
+  double *Bt = nullptr, *Voooo, *Vooov, *Voovv, *Voovv_p, *Vvovo, *Vvovv_p;
+  double *x, *diis, *T2, *TAU, *taup, *Tq, *Xp, *H4, *R, *Zij, *Zab, *Znp;
+  double *Hac, *Gac, *Hki, *Gki, *Hkc, *y, *Zt, *U, *Vt, *M1, *Y, *S1, *Cp, *Cf, *Af, *Ap;
+  double *Ta, *W;
+  double* red = nullptr;      // reduction partials
+  double* redout = nullptr;   // reduced values (device)
+  double* host = nullptr;     // pinned readback
+  int* rowmap_o = nullptr;    // k*o+l for pairs k<l
+  // DIIS state
+  std::vector<int> order;     // slot ids, oldest first
+  std::vector<std::vector<zc>> G;
+  double first_norm = -1.0;
+  zc energy = 0.0;
+  int iters = 0;
+  Timer tm;
+
+  double* slot_x(int k) { return diis + (int64_t)2 * k * 2 * P.L; }
+  double* slot_e(int k) { return diis + ((int64_t)2 * k + 1) * 2 * P.L; }
+
+  ~Handle() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (host) (void)hipHostFree(host);
+    for (auto e : tm.pool) (void)hipEventDestroy(e);
+    if (own_stream && s) (void)hipStreamDestroy(s);
+  }
+  void use() { set_alloc_registry(ranges.data(), (int)ranges.size()); }
+  double* dalloc(int64_t complex_elems) {
+    void* p = nullptr;
+    const size_t b = (size_t)std::max<int64_t>(complex_elems, 1) * 16;
+    HIPCHECK(hipMalloc(&p, b));
+    allocs.push_back(p);
+    ranges.push_back({p, b});
+    set_alloc_registry(ranges.data(), (int)ranges.size());
+    return (double*)p;
+  }
+};
+
+struct Scope {  // event-bracketed stage (only with opts.timing)
+  Handle& h;
+  int id;
+  hipEvent_t a{}, b{};
+  Scope(Handle& hh, const char* nm) : h(hh), id(-1) {
+    if (!h.tm.on) return;
+    id = h.tm.id(nm);
+    a = h.tm.ev();
+    b = h.tm.ev();
+    HIPCHECK(hipEventRecord(a, h.s));
+  }
+  ~Scope() {
+    if (id < 0) return;
+    (void)hipEventRecord(b, h.s);
+    h.tm.pending.push_back({id, {a, b}});
+  }
+};
+
+static void timer_collect(Handle& h) {
+  if (!h.tm.on) return;
+  for (auto& pe : h.tm.pending) {
+    float ms = 0;
+    HIPCHECK(hipEventSynchronize(pe.second.second));
+    HIPCHECK(hipEventElapsedTime(&ms, pe.second.first, pe.second.second));
+    h.tm.ms[pe.first] += ms;
+  }
+  h.tm.pending.clear();
+  h.tm.used = 0;
+}
+
+static const cplx ONE{1, 0}, MONE{-1, 0}, HALF{0.5, 0};
+
+// ------------------------------------------------------------------ views
+struct Views {
+  TV<double> Bvv, Bov, Bvo, Boo;
+};
+static Views bviews(Handle& h) {
+  const int o = h.P.o, v = h.P.v, X = h.P.X, n = h.P.n;
+  Views w;
+  const int64_t nX = (int64_t)n * X;
+  w.Boo = sview(h.Bt, {o, o, X}, {nX, X, 1});
+  w.Bov = sview(h.Bt + 2 * (int64_t)o * X, {o, v, X}, {nX, X, 1});
+  w.Bvo = sview(h.Bt + 2 * (int64_t)o * nX, {v, o, X}, {nX, X, 1});
+  w.Bvv = sview(h.Bt + 2 * ((int64_t)o * nX + (int64_t)o * X), {v, v, X}, {nX, X, 1});
+  return w;
+}
+
+static void dcopy(Handle& h, double* dst, const double* src, int64_t celems) {
+  if (celems > 0) HIPCHECK(hipMemcpyAsync(dst, src, celems * 16, hipMemcpyDeviceToDevice, h.s));
+}
+
+// ------------------------------------------------------------------ integrals (create)
+static void build_integrals(Handle& h, double* vovv_tmp) {
+  Scope sc(h, "integrals");
+  const int o = h.P.o, v = h.P.v;
+  const hipStream_t s = h.s;
+  Views b = bviews(h);
+  // <kl||ij> = (ki|lj) - (kj|li)
+  auto Voooo = view(h.Voooo, {o, o, o, o});
+  contract(s, "kiP,ljP->klij", ONE, b.Boo, b.Boo, false, Voooo);
+  contract(s, "kjP,liP->klij", MONE, b.Boo, b.Boo, true, Voooo);
+  // <kl||ic> = (ki|lc) - (kc|li)
+  auto Vooov = view(h.Vooov, {o, o, o, v});
+  contract(s, "kiP,lcP->klic", ONE, b.Boo, b.Bov, false, Vooov);
+  contract(s, "kcP,liP->klic", MONE, b.Bov, b.Boo, true, Vooov);
+  // <kl||cd> = (kc|ld) - (kd|lc)
+  auto Voovv = view(h.Voovv, {o, o, v, v});
+  contract(s, "kcP,ldP->klcd", ONE, b.Bov, b.Bov, false, Voovv);
+  contract(s, "kdP,lcP->klcd", MONE, b.Bov, b.Bov, true, Voovv);
+  // <ak||ci> = (ac|ki) - (ai|kc), stored as [a][i][k][c]
+  auto Vvovo = view(h.Vvovo, {v, o, o, v});
+  contract(s, "acP,kiP->aikc", ONE, b.Bvv, b.Boo, false, Vvovo);
+  contract(s, "aiP,kcP->aikc", MONE, b.Bvo, b.Bov, true, Vvovo);
+  // packed <ij||ab>, i<j, a<b
+  if (h.P.Po > 0) k_pack_last2(h.Voovv_p, h.Voovv, h.rowmap_o, h.P.Po, v, h.P.vv, s);
+  // <bk||cd> = (bc|kd) - (bd|kc), packed over c<d, rows (b, k); built in chunks of b
+  if (h.P.Pv > 0) {
+    const int64_t nX = (int64_t)h.P.n * h.P.X;
+    for (int b0 = 0; b0 < v; b0 += (int)h.P.vovv_chunk) {
+      const int nb = (int)std::min<int64_t>(h.P.vovv_chunk, v - b0);
+      auto Bc = sview(b.Bvv.p + 2 * (int64_t)b0 * nX, {nb, v, h.P.X}, {nX, h.P.X, 1});
+      auto tmp = view(vovv_tmp, {nb, o, v, v});
+      contract(s, "bcP,kdP->bkcd", ONE, Bc, b.Bov, false, tmp);
+      contract(s, "bdP,kcP->bkcd", MONE, Bc, b.Bov, true, tmp);
+      k_pack_last2(h.Vvovv_p + 2 * (int64_t)b0 * o * h.P.Pv, vovv_tmp, nullptr, (int64_t)nb * o, v,
+                   h.P.vv, s);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ residual pieces
+// Fills S1 (singles, without the diagonal Fock part) and the doubles pieces
+// Znp (no permutation), Zab (P_ab), Zij (P_ij), R (P_ij P_ab) for the
+// amplitudes in h.x.
+static void compute_residual(Handle& h) {
+  const int o = h.P.o, v = h.P.v, X = h.P.X;
+  const int64_t Po = h.P.Po, Pv = h.P.Pv;
+  const hipStream_t s = h.s;
+  Views b = bviews(h);
+  const double* t1p = h.x;
+  const double* t2p = h.x + 2 * (int64_t)o * v;
+  auto t1 = view((double*)t1p, {o, v});
+  auto T2 = view(h.T2, {o, o, v, v});
+  auto TAU = view(h.TAU, {o, o, v, v});
+  auto taup = view(h.taup, {Po, Pv});
+  auto Voovv = view(h.Voovv, {o, o, v, v});
+  auto Vooov = view(h.Vooov, {o, o, o, v});
+  auto Vvovo = view(h.Vvovo, {v, o, o, v});
+  {
+    Scope sc(h, "prep");
+    k_unpack_tau(t1p, t2p, h.T2, h.TAU, h.taup, o, v, s);
+    k_ring_operands(h.T2, t1p, h.Tq, h.Xp, o, v, s);
+  }
+  auto Hac = view(h.Hac, {v, v}), Gac = view(h.Gac, {v, v});
+  auto Hki = view(h.Hki, {o, o}), Gki = view(h.Gki, {o, o});
+  auto Hkc = view(h.Hkc, {o, v});
+  {
+    Scope sc(h, "onebody");
+    contract(s, "klcd,klda->ac", HALF, Voovv, TAU, false, Hac);
+    contract(s, "klcd,licd->ki", HALF, Voovv, TAU, false, Hki);
+    contract(s, "klcd,ld->kc", ONE, Voovv, t1, false, Hkc);
+    dcopy(h, h.Gac, h.Hac, (int64_t)v * v);
+    dcopy(h, h.Gki, h.Hki, (int64_t)o * o);
+    // sum_kd <ak||cd> t_k^d = sum_P B_ac^P (sum_kd B_kd^P t_k^d) - sum_Pd B_ad^P (sum_k t_k^d B_kc^P)
+    auto y = view(h.y, {X});
+    contract(s, "kdP,kd->P", ONE, b.Bov, t1, false, y);
+    contract(s, "acP,P->ac", ONE, b.Bvv, y, true, Gac);
+    auto Zt = view(h.Zt, {v, v, X});
+    contract(s, "kd,kcP->dcP", ONE, t1, b.Bov, false, Zt);
+    contract(s, "adP,dcP->ac", MONE, b.Bvv, Zt, true, Gac);
+    contract(s, "klic,lc->ki", MONE, Vooov, t1, true, Gki);
+  }
+  auto H4 = view(h.H4, {v, o, o, v});
+  auto U = view(h.U, {o, o, X});
+  auto Vt = view(h.Vt, {v, o, X});
+  {
+    Scope sc(h, "ring_build");
+    dcopy(h, h.H4, h.Vvovo, h.P.oovv);
+    contract(s, "kdP,id->kiP", ONE, b.Bov, t1, false, U);
+    contract(s, "acP,ic->aiP", ONE, b.Bvv, t1, false, Vt);
+    contract(s, "acP,kiP->aikc", ONE, b.Bvv, U, true, H4);
+    contract(s, "aiP,kcP->aikc", MONE, Vt, b.Bov, true, H4);
+    contract(s, "klic,la->aikc", MONE, Vooov, t1, true, H4);
+    contract(s, "aild,klcd->aikc", ONE, view(h.Xp, {v, o, o, v}), Voovv, true, H4, GETT_RING);
+  }
+  auto R = view(h.R, {o, o, v, v});
+  {
+    Scope sc(h, "ring");
+    contract(s, "aikc,bjkc->ijab", ONE, H4, view(h.Tq, {v, o, o, v}), false, R, GETT_RING);
+    contract(s, "aiP,bjP->ijab", ONE, Vt, b.Bvo, true, R);
+  }
+  auto Zij = view(h.Zij, {o, o, v, v});
+  auto Zab = view(h.Zab, {o, o, v, v});
+  {
+    Scope sc(h, "fock_terms");
+    contract(s, "kj,ikab->ijab", ONE, Gki, T2, false, Zij);
+    contract(s, "ac,ijcb->ijab", ONE, Gac, T2, false, Zab);
+  }
+  {
+    Scope sc(h, "cterm");
+    auto Cp = view(h.Cp, {Po, v, o});
+    contract(s, "bkx,px->pbk", MONE, view(h.Vvovv_p, {v, o, Pv}), taup, false, Cp);
+    k_expand_c(h.Vooov, h.Cp, h.Cf, o, v, s);
+    auto Cf = view(h.Cf, {o, o, v, o});
+    contract(s, "bikc,jc->ijbk", ONE, Vvovo, t1, true, Cf);
+    contract(s, "bjkc,ic->ijbk", MONE, Vvovo, t1, true, Cf);
+    contract(s, "ijak,kb->ijab", ONE, Cf, t1, true, Zab);
+  }
+  auto Znp = view(h.Znp, {Po, Pv});
+  {
+    Scope sc(h, "hole_ladder");
+    auto Af = view(h.Af, {o, o, o, o});
+    dcopy(h, h.Af, h.Voooo, (int64_t)o * o * o * o);
+    contract(s, "klic,jc->klij", ONE, Vooov, t1, true, Af);
+    contract(s, "kljc,ic->klij", MONE, Vooov, t1, true, Af);
+    contract(s, "klcd,ijcd->klij", HALF, Voovv, TAU, true, Af);
+    if (Po > 0) k_pack_last2(h.Ap, h.Af, h.rowmap_o, Po, o, (int64_t)o * o, s);
+    contract(s, "qp,qx->px", ONE, view(h.Ap, {Po, Po}), taup, false, Znp);
+  }
+  // particle ladder: Znp[ij][ab] += sum_{c<d} tau[ij][cd] <ab||cd>, <ab||cd> = (ac|bd) - (ad|bc)
+  if (Po > 0 && Pv > 0) {
+    const int64_t nX = (int64_t)h.P.n * X;
+    int64_t rows = 0, start = 0;
+    auto flush = [&]() {
+      if (rows == 0) return;
+      Scope sc(h, "ladder_contract");
+      auto Wv = view(h.W, {rows, Pv});
+      auto Zc = sview(h.Znp + 2 * start, {Po, rows}, {Pv, 1});
+      contract(s, "py,xy->px", ONE, taup, Wv, true, Zc, GETT_LADDER_CONTRACT);
+      start += rows;
+      rows = 0;
+    };
+    for (int a = 0; a + 1 < v; ++a) {
+      const int nb = v - a - 1;
+      if (rows + nb > h.P.chunk_pairs) flush();
+      {
+        Scope sc(h, "ladder_build");
+        auto Ba = sview(b.Bvv.p + 2 * (int64_t)a * nX, {v, X}, {X, 1});
+        auto Bb = sview(b.Bvv.p + 2 * (int64_t)(a + 1) * nX, {nb, v, X}, {nX, X, 1});
+        contract(s, "cP,bdP->cbd", ONE, Ba, Bb, false, view(h.Ta, {v, nb, v}), GETT_LADDER_BUILD);
+      }
+      {
+        Scope sc(h, "ladder_antisym");
+        k_ladder_antisym(h.Ta, h.W + 2 * rows * Pv, nb, v, s);
+      }
+      rows += nb;
+    }
+    flush();
+  }
+  {
+    Scope sc(h, "singles");
+    auto S1 = view(h.S1, {o, v});
+    contract(s, "ac,ic->ia", ONE, Hac, t1, false, S1);
+    contract(s, "ki,ka->ia", ONE, Hki, t1, true, S1);
+    contract(s, "kc,ikac->ia", ONE, Hkc, T2, true, S1);
+    auto M1 = view(h.M1, {o, o});
+    contract(s, "kc,ic->ki", ONE, Hkc, t1, false, M1);
+    contract(s, "ki,ka->ia", ONE, M1, t1, true, S1);
+    auto Y = view(h.Y, {o, v, X});
+    contract(s, "ikcd,kdP->icP", ONE, TAU, b.Bov, false, Y);
+    contract(s, "icP,acP->ia", ONE, Y, b.Bvv, true, S1);
+    contract(s, "klic,klca->ia", HALF, Vooov, TAU, true, S1);
+    contract(s, "aikc,kc->ia", MONE, Vvovo, t1, true, S1);
+  }
+}
+
+// ------------------------------------------------------------------ small host linear algebra
+// Eigenvalues of a Hermitian m x m matrix via cyclic Jacobi on its real 2m x 2m embedding.
+static std::vector<double> herm_eigvals(const std::vector<std::vector<zc>>& Gm) {
+  const int m = (int)Gm.size(), N = 2 * m;
+  std::vector<double> a(N * N);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      const double re = Gm[i][j].real(), im = Gm[i][j].imag();
+      a[i * N + j] = re;
+      a[(i + m) * N + (j + m)] = re;
+      a[i * N + (j + m)] = -im;
+      a[(i + m) * N + j] = im;
+    }
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0, tot = 0;
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        tot += a[i * N + j] * a[i * N + j];
+        if (i != j) off += a[i * N + j] * a[i * N + j];
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < N; ++p)
+      for (int q = p + 1; q < N; ++q) {
+        const double apq = a[p * N + q];
+        if (apq == 0.0) continue;
+        const double theta = (a[q * N + q] - a[p * N + p]) / (2 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1));
+        const double c = 1 / std::sqrt(t * t + 1), sn = t * c;
+        for (int k = 0; k < N; ++k) {
+          const double akp = a[k * N + p], akq = a[k * N + q];
+          a[k * N + p] = c * akp - sn * akq;
+          a[k * N + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < N; ++k) {
+          const double apk = a[p * N + k], aqk = a[q * N + k];
+          a[p * N + k] = c * apk - sn * aqk;
+          a[q * N + k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  std::vector<double> w(N);
+  for (int i = 0; i < N; ++i) w[i] = a[i * N + i];
+  std::sort(w.begin(), w.end());
+  std::vector<double> out(m);
+  for (int i = 0; i < m; ++i) out[i] = w[2 * i];  // each eigenvalue appears twice
+  return out;
+}
+
+// Solve the (m+1) bordered DIIS system [[G, 1], [1^T, 0]] [c; lam] = [0; 1].
+static std::vector<zc> diis_solve(const std::vector<std::vector<zc>>& Gm) {
+  const int m = (int)Gm.size(), N = m + 1;
+  std::vector<zc> A(N * N, 0.0), r(N, 0.0);
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < m; ++j) A[i * N + j] = Gm[i][j];
+    A[i * N + m] = 1.0;
+    A[m * N + i] = 1.0;
+  }
+  r[m] = 1.0;
+  for (int c = 0; c < N; ++c) {
+    int piv = c;
+    for (int i = c + 1; i < N; ++i)
+      if (std::abs(A[i * N + c]) > std::abs(A[piv * N + c])) piv = i;
+    if (piv != c) {
+      for (int j = 0; j < N; ++j) std::swap(A[c * N + j], A[piv * N + j]);
+      std::swap(r[c], r[piv]);
+    }
+    const zc d = A[c * N + c];
+    for (int i = c + 1; i < N; ++i) {
+      const zc f = A[i * N + c] / d;
+      if (f == 0.0) continue;
+      for (int j = c; j < N; ++j) A[i * N + j] -= f * A[c * N + j];
+      r[i] -= f * r[c];
+    }
+  }
+  for (int i = N - 1; i >= 0; --i) {
+    zc acc = r[i];
+    for (int j = i + 1; j < N; ++j) acc -= A[i * N + j] * r[j];
+    r[i] = acc / A[i * N + i];
+  }
+  r.resize(m);
+  return r;
+}
+
+// ------------------------------------------------------------------ one iteration
+static zc device_energy(Handle& h) {
+  Scope sc(h, "energy");
+  const int o = h.P.o, v = h.P.v;
+  const int64_t np = h.P.Po * h.P.Pv;
+  if (np == 0) return 0.0;  // f_ia = 0: no singles term
+  const int nb = energy_blocks(np);
+  k_energy(h.Voovv_p, h.x + 2 * (int64_t)o * v, h.x, o, v, h.red, nb, h.s);
+  k_reduce_sum(h.red, nb, 2, h.redout, h.s);
+  HIPCHECK(hipMemcpyAsync(h.host, h.redout, 16, hipMemcpyDeviceToHost, h.s));
+  HIPCHECK(hipStreamSynchronize(h.s));
+  return zc(h.host[0], h.host[1]);
+}
+
+static double one_iteration(Handle& h) {
+  const int o = h.P.o, v = h.P.v;
+  const int64_t ov = (int64_t)o * v, L = h.P.L;
+  compute_residual(h);
+  // pick the DIIS slot (drop the oldest pair when full)
+  const int cap = h.P.nslots;
+  if ((int)h.order.size() == cap) {
+    h.order.erase(h.order.begin());
+  }
+  int slot = 0;
+  for (; slot < cap; ++slot)
+    if (std::find(h.order.begin(), h.order.end(), slot) == h.order.end()) break;
+  double* xt = h.slot_x(slot);
+  double* e = h.slot_e(slot);
+  {
+    Scope sc(h, "assemble");
+    k_assemble_t1(h.S1, h.x, h.eps, o, v, h.op.level_shift, xt, e, nullptr, h.red, h.s);
+    const int64_t np = h.P.Po * h.P.Pv;
+    int nb = 0;
+    if (np > 0) {
+      nb = assemble_t2_blocks(np);
+      k_assemble_t2(h.Znp, h.Zab, h.Zij, h.R, h.Voovv_p, h.x + 2 * ov, h.eps, o, v, h.op.level_shift,
+                    xt + 2 * ov, e + 2 * ov, nullptr, h.red + 1, nb, h.s);
+    }
+    k_reduce_sum(h.red, nb + 1, 1, h.redout, h.s);
+  }
+  // Gram row of the new error vector against every stored one (and itself)
+  std::vector<int> ids = h.order;
+  ids.push_back(slot);
+  const int m = (int)ids.size();
+  if (h.op.diis_size > 0) {
+    Scope sc(h, "diis");
+    std::vector<const double*> es;
+    for (int k : ids) es.push_back(h.slot_e(k));
+    const int nb = dot_many_blocks(L);
+    k_dot_many(es.data(), m, e, L, h.red + 8192, nb, h.s);
+    k_reduce_sum(h.red + 8192, nb, 2 * m, h.redout + 8, h.s);
+  }
+  HIPCHECK(hipMemcpyAsync(h.host, h.redout, (8 + 2 * m) * sizeof(double), hipMemcpyDeviceToHost, h.s));
+  HIPCHECK(hipStreamSynchronize(h.s));
+  const double rnorm = std::sqrt(h.host[0]);
+  h.order.push_back(slot);
+  if ((int)h.G.size() < cap) h.G.assign(cap, std::vector<zc>(cap, 0.0));
+  if (h.op.diis_size > 0)
+    for (int k = 0; k < m; ++k) {
+      const zc g(h.host[8 + 2 * k], h.host[8 + 2 * k + 1]);  // <e_k, e_new>
+      h.G[ids[k]][slot] = g;
+      h.G[slot][ids[k]] = std::conj(g);
+    }
+  // coefficients: drop the oldest while the subspace is ill-conditioned
+  std::vector<zc> c;
+  while (h.op.diis_size > 0 && h.order.size() >= 2) {
+    const int mm = (int)h.order.size();
+    std::vector<std::vector<zc>> Gm(mm, std::vector<zc>(mm));
+    for (int i = 0; i < mm; ++i)
+      for (int j = 0; j < mm; ++j) Gm[i][j] = h.G[h.order[i]][h.order[j]];
+    const std::vector<double> w = herm_eigvals(Gm);
+    if (!(w[0] > 0.0) || w[mm - 1] / w[0] > 1e14) {
+      h.order.erase(h.order.begin());
+      continue;
+    }
+    c = diis_solve(Gm);
+    break;
+  }
+  if (c.empty()) c.assign(h.order.size(), 1.0);
+  {
+    Scope sc(h, "diis");
+    std::vector<const double*> xs;
+    std::vector<cplx> cc;
+    for (size_t k = 0; k < h.order.size(); ++k) {
+      xs.push_back(h.slot_x(h.order[k]));
+      cc.push_back(cplx{c[k].real(), c[k].imag()});
+    }
+    k_lincomb(h.x, xs.data(), cc.data(), (int)xs.size(), L, h.s);
+  }
+  h.energy = device_energy(h);
+  timer_collect(h);
+  h.iters++;
+  return rnorm;
+}
+
+static void reset_diis(Handle& h) {
+  h.order.clear();
+  h.G.clear();
+  h.first_norm = -1.0;
+}
+
+// ------------------------------------------------------------------ create
+static void validate_host_inputs(int o, int v, const double* eps) {
+  double emax = -1e300, emin = 1e300;
+  for (int i = 0; i < o + v; ++i)
+    if (!std::isfinite(eps[i])) raise(EXACC_ERR_INVALID_ARG, "non-finite spinor energy");
+  for (int i = 0; i < o; ++i) emax = std::max(emax, eps[i]);
+  for (int a = 0; a < v; ++a) emin = std::min(emin, eps[o + a]);
+  if (!(emin - emax > 1e-8)) raise(EXACC_ERR_INVALID_ARG, "no gap between occupied and virtual energies");
+}
+
+static Handle* create_impl(int o, int v, int X, const double* eps, const double* B,
+                           const exacc_ccsd_opts& op) {
+  if (o < 1 || v < 1 || X < 1) raise(EXACC_ERR_INVALID_ARG, "nocc, nvir and naux must be >= 1");
+  if (!eps || !B) raise(EXACC_ERR_INVALID_ARG, "null input pointer");
+  if ((int64_t)o * o > 65535) raise(EXACC_ERR_INVALID_ARG, "nocc too large (nocc^2 > 65535)");
+  if (op.precision != EXACC_FP64) raise(EXACC_ERR_UNSUPPORTED, "only EXACC_FP64 is built");
+  if (op.diis_size < 0 || op.diis_size > 16) raise(EXACC_ERR_INVALID_ARG, "diis_size must be 0..16");
+  if (!(op.tol >= 0) || !std::isfinite(op.level_shift))
+    raise(EXACC_ERR_INVALID_ARG, "bad tol or level_shift");
+  Plan P = make_plan(o, v, X, op);
+  if (op.hbm_budget_bytes && P.bytes_peak > op.hbm_budget_bytes)
+    raise(EXACC_ERR_NOMEM, "memory plan exceeds hbm_budget_bytes");
+  Handle* h = new Handle();
+  try {
+    h->P = P;
+    h->op = op;
+    h->tm.on = op.timing != 0;
+    if (op.stream) {
+      h->s = (hipStream_t)op.stream;
+    } else {
+      HIPCHECK(hipStreamCreateWithFlags(&h->s, hipStreamNonBlocking));
+      h->own_stream = true;
+    }
+    const int n = o + v;
+    const int64_t nnX = (int64_t)n * n * X;
+    HIPCHECK(hipHostMalloc((void**)&h->host, 4096 * sizeof(double), hipHostMallocDefault));
+    // eps: validate on the host
+    std::vector<double> eh(n);
+    if (op.inputs_on_device)
+      HIPCHECK(hipMemcpy(eh.data(), eps, n * sizeof(double), hipMemcpyDeviceToHost));
+    else
+      std::memcpy(eh.data(), eps, n * sizeof(double));
+    validate_host_inputs(o, v, eh.data());
+    h->eps = (double*)h->dalloc((n + 1) / 2);
+    HIPCHECK(hipMemcpyAsync(h->eps, eh.data(), n * sizeof(double), hipMemcpyHostToDevice, h->s));
+    h->red = h->dalloc(65536);
+    h->redout = h->dalloc(64);
+    // B: stage raw, check Hermiticity and finiteness on the device, transpose to [p][q][P]
+    const double* Braw = B;
+    double* Bstage = nullptr;
+    if (!op.inputs_on_device) {
+      HIPCHECK(hipMalloc((void**)&Bstage, nnX * 16));
+      HIPCHECK(hipMemcpyAsync(Bstage, B, nnX * 16, hipMemcpyHostToDevice, h->s));
+      Braw = Bstage;
+    }
+    struct Free {
+      double* p;
+      ~Free() {
+        if (p) (void)hipFree(p);
+      }
+    } fb{Bstage};
+    k_check_B(Braw, X, n, h->redout, h->red, h->s);
+    HIPCHECK(hipMemcpyAsync(h->host, h->redout, 3 * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPCHECK(hipStreamSynchronize(h->s));
+    if (h->host[2] != 0.0) raise(EXACC_ERR_INVALID_ARG, "non-finite entries in B");
+    if (h->host[0] > 1e-12 * std::max(h->host[1], 1e-300))
+      raise(EXACC_ERR_INVALID_ARG, "B[P] is not Hermitian");
+    h->Bt = h->dalloc(nnX);
+    k_transpose_B(Braw, h->Bt, X, (int64_t)n * n, h->s);
+    HIPCHECK(hipStreamSynchronize(h->s));
+    if (Bstage) {
+      HIPCHECK(hipFree(Bstage));
+      fb.p = nullptr;
+    }
+    const int64_t oo = (int64_t)o * o;
+    h->Voooo = h->dalloc(oo * oo);
+    h->Vooov = h->dalloc(oo * o * v);
+    h->Voovv = h->dalloc(P.oovv);
+    h->Voovv_p = h->dalloc(P.Po * P.Pv);
+    h->Vvovo = h->dalloc(P.oovv);
+    h->Vvovv_p = h->dalloc((int64_t)v * o * P.Pv);
+    h->x = h->dalloc(P.L);
+    h->diis = h->dalloc(2 * P.nslots * P.L);
+    h->T2 = h->dalloc(P.oovv);
+    h->TAU = h->dalloc(P.oovv);
+    h->taup = h->dalloc(P.Po * P.Pv);
+    h->Tq = h->dalloc(P.oovv);
+    h->Xp = h->dalloc(P.oovv);
+    h->H4 = h->dalloc(P.oovv);
+    h->R = h->dalloc(P.oovv);
+    h->Zij = h->dalloc(P.oovv);
+    h->Zab = h->dalloc(P.oovv);
+    h->Znp = h->dalloc(P.Po * P.Pv);
+    h->Hac = h->dalloc(P.vv);
+    h->Gac = h->dalloc(P.vv);
+    h->Hki = h->dalloc(oo);
+    h->Gki = h->dalloc(oo);
+    h->M1 = h->dalloc(oo);
+    h->Hkc = h->dalloc((int64_t)o * v);
+    h->S1 = h->dalloc((int64_t)o * v);
+    h->y = h->dalloc(X);
+    h->Zt = h->dalloc(P.vv * X);
+    h->U = h->dalloc(oo * X);
+    h->Vt = h->dalloc((int64_t)v * o * X);
+    h->Y = h->dalloc((int64_t)o * v * X);
+    h->Cp = h->dalloc(P.Po * v * o);
+    h->Cf = h->dalloc(oo * v * o);
+    h->Af = h->dalloc(oo * oo);
+    h->Ap = h->dalloc(P.Po * P.Po);
+    h->Ta = h->dalloc((int64_t)v * std::max(1, v - 1) * v);
+    h->W = h->dalloc(P.chunk_pairs * std::max<int64_t>(1, P.Pv));
+    {
+      std::vector<int> rm;
+      for (int k = 0; k < o; ++k)
+        for (int l = k + 1; l < o; ++l) rm.push_back(k * o + l);
+      void* p = nullptr;
+      HIPCHECK(hipMalloc(&p, std::max<size_t>(1, rm.size()) * sizeof(int)));
+      h->allocs.push_back(p);
+      h->rowmap_o = (int*)p;
+      if (!rm.empty())
+        HIPCHECK(hipMemcpyAsync(h->rowmap_o, rm.data(), rm.size() * sizeof(int), hipMemcpyHostToDevice,
+                                h->s));
+    }
+    {
+      double* tmp = nullptr;
+      HIPCHECK(hipMalloc((void**)&tmp, std::max<int64_t>(1, P.vovv_chunk * o * P.vv) * 16));
+      Free ft{tmp};
+      h->ranges.push_back({tmp, (size_t)std::max<int64_t>(1, P.vovv_chunk * o * P.vv) * 16});
+      h->use();
+      build_integrals(*h, tmp);
+      HIPCHECK(hipStreamSynchronize(h->s));
+      h->ranges.pop_back();
+      h->use();
+    }
+    HIPCHECK(hipMemsetAsync(h->x, 0, P.L * 16, h->s));
+    HIPCHECK(hipStreamSynchronize(h->s));
+    timer_collect(*h);
+    return h;
+  } catch (...) {
+    if (h->s) (void)hipStreamSynchronize(h->s);
+    set_alloc_registry(nullptr, 0);
+    delete h;
+    throw;
+  }
+}
+
+}  // namespace exacc
+
+// ====================================================================== C ABI
+using namespace exacc;
+
+template <typename F>
+static int guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return EXACC_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return EXACC_ERR_DEVICE;
+  }
+}
+
+extern "C" {
+
+void exacc_ccsd_default_opts(exacc_ccsd_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->precision = EXACC_FP64;
+  o->diis_size = 8;
+  o->max_iter = 30;
+  o->tol = 1e-9;
+  o->level_shift = 0.0;
+  o->fp64_final_iters = 3;
+  o->mixed_switch_tol = 1e-5;
+}
+
+size_t exacc_ccsd_memory_estimate(int nocc, int nvir, int naux, const exacc_ccsd_opts* opts) {
+  if (nocc < 1 || nvir < 1 || naux < 1) return 0;
+  exacc_ccsd_opts d;
+  exacc_ccsd_default_opts(&d);
+  return make_plan(nocc, nvir, naux, opts ? *opts : d).bytes_peak;
+}
+
+int exacc_ccsd_create(exacc_ccsd_t* out, int nocc, int nvir, int naux, const double* eps,
+                      const double* B, const exacc_ccsd_opts* opts) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!out) raise(EXACC_ERR_INVALID_ARG, "null handle pointer");
+    exacc_ccsd_opts d;
+    exacc_ccsd_default_opts(&d);
+    Handle* h = create_impl(nocc, nvir, naux, eps, B, opts ? *opts : d);
+    *out = reinterpret_cast<exacc_ccsd_t>(h);
+    return EXACC_OK;
+  });
+}
+
+int exacc_ccsd_iterate(exacc_ccsd_t hh, int max_steps, int* steps_done, double* residual,
+                       int* converged) {
+  if (steps_done) *steps_done = 0;
+  if (converged) *converged = 0;
+  return guarded([&] {
+    if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    h.use();
+    for (int k = 0; k < max_steps; ++k) {
+      const double r = one_iteration(h);
+      if (steps_done) *steps_done = k + 1;
+      if (residual) *residual = r;
+      if (h.first_norm < 0) h.first_norm = r;
+      if (!std::isfinite(r) || !std::isfinite(h.energy.real()) || !std::isfinite(h.energy.imag()) ||
+          r > 1e6 * std::max(h.first_norm, 1e-300))
+        return (int)EXACC_ERR_DIVERGED;
+      if (r <= h.op.tol) {
+        if (converged) *converged = 1;
+        return (int)EXACC_OK;
+      }
+    }
+    return (int)EXACC_NOT_CONVERGED;
+  });
+}
+
+int exacc_ccsd_energy(exacc_ccsd_t hh, double* e_re, double* e_im) {
+  return guarded([&] {
+    if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    h.use();
+    const zc e = device_energy(h);
+    timer_collect(h);
+    if (e_re) *e_re = e.real();
+    if (e_im) *e_im = e.imag();
+    return (int)EXACC_OK;
+  });
+}
+
+int exacc_ccsd_get_amplitudes(exacc_ccsd_t hh, double* t1, double* t2, int on_device) {
+  return guarded([&] {
+    if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    h.use();
+    const int o = h.P.o, v = h.P.v;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (t1) HIPCHECK(hipMemcpyAsync(t1, h.x, (size_t)o * v * 16, k, h.s));
+    if (t2) {
+      k_unpack_full(h.x, h.x + 2 * (int64_t)o * v, nullptr, h.T2, o, v, h.s);
+      HIPCHECK(hipMemcpyAsync(t2, h.T2, (size_t)h.P.oovv * 16, k, h.s));
+    }
+    HIPCHECK(hipStreamSynchronize(h.s));
+    return (int)EXACC_OK;
+  });
+}
+
+int exacc_ccsd_set_amplitudes(exacc_ccsd_t hh, const double* t1, const double* t2, int on_device) {
+  return guarded([&] {
+    if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    h.use();
+    const int o = h.P.o, v = h.P.v;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (t1)
+      HIPCHECK(hipMemcpyAsync(h.x, t1, (size_t)o * v * 16, k, h.s));
+    else
+      HIPCHECK(hipMemsetAsync(h.x, 0, (size_t)o * v * 16, h.s));
+    if (t2) {
+      HIPCHECK(hipMemcpyAsync(h.T2, t2, (size_t)h.P.oovv * 16, k, h.s));
+      k_pack_amplitudes(nullptr, h.T2, h.x + 2 * (int64_t)o * v, o, v, h.s);
+    } else if (h.P.Po * h.P.Pv > 0) {
+      HIPCHECK(hipMemsetAsync(h.x + 2 * (int64_t)o * v, 0, (size_t)h.P.Po * h.P.Pv * 16, h.s));
+    }
+    HIPCHECK(hipStreamSynchronize(h.s));
+    reset_diis(h);
+    return (int)EXACC_OK;
+  });
+}
+
+int exacc_ccsd_residual(exacc_ccsd_t hh, double* s1, double* s2, int on_device) {
+  return guarded([&] {
+    if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    h.use();
+    const int o = h.P.o, v = h.P.v;
+    compute_residual(h);
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    // reuse Tq as the full S2 buffer and Hkc as S1 output (both are rebuilt each iteration)
+    if (s1) {
+      k_assemble_t1(h.S1, h.x, h.eps, o, v, 0.0, nullptr, nullptr, h.Hkc, nullptr, h.s);
+      HIPCHECK(hipMemcpyAsync(s1, h.Hkc, (size_t)o * v * 16, k, h.s));
+    }
+    if (s2) {
+      HIPCHECK(hipMemsetAsync(h.Tq, 0, (size_t)h.P.oovv * 16, h.s));
+      const int64_t np = h.P.Po * h.P.Pv;
+      if (np > 0)
+        k_assemble_t2(h.Znp, h.Zab, h.Zij, h.R, h.Voovv_p, h.x + 2 * (int64_t)o * v, h.eps, o, v, 0.0,
+                      nullptr, nullptr, h.Tq, nullptr, assemble_t2_blocks(np), h.s);
+      HIPCHECK(hipMemcpyAsync(s2, h.Tq, (size_t)h.P.oovv * 16, k, h.s));
+    }
+    HIPCHECK(hipStreamSynchronize(h.s));
+    timer_collect(h);
+    return (int)EXACC_OK;
+  });
+}
+
+int exacc_ccsd_stage_times(exacc_ccsd_t hh, const char** names, double* ms, int* count, int reset) {
+  return guarded([&] {
+    if (!hh || !count) raise(EXACC_ERR_INVALID_ARG, "null argument");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    const int cap = *count;
+    const int nn = (int)h.tm.names.size();
+    for (int i = 0; i < nn && i < cap; ++i) {
+      if (names) names[i] = h.tm.names[i].c_str();
+      if (ms) ms[i] = h.tm.ms[i];
+    }
+    *count = nn;
+    if (reset)
+      for (auto& x : h.tm.ms) x = 0.0;
+    return (int)EXACC_OK;
+  });
+}
+
+double exacc_ladder_flops(int nocc, int nvir, int naux) {
+  const double Po = 0.5 * nocc * (nocc - 1.0), Pv = 0.5 * nvir * (nvir - 1.0);
+  return 8.0 * (2.0 * naux * Pv * Pv + Po * Pv * Pv);
+}
+
+int exacc_ccsd_destroy(exacc_ccsd_t hh) {
+  if (!hh) return EXACC_OK;
+  return guarded([&] {
+    Handle* h = reinterpret_cast<Handle*>(hh);
+    if (h->s) (void)hipStreamSynchronize(h->s);
+    set_alloc_registry(nullptr, 0);
+    delete h;
+    return (int)EXACC_OK;
+  });
+}
+
+const char* exacc_status_string(int st) {
+  switch (st) {
+    case EXACC_OK: return "ok";
+    case EXACC_NOT_CONVERGED: return "not converged";
+    case EXACC_ERR_INVALID_ARG: return "invalid argument";
+    case EXACC_ERR_NOMEM: return "out of device memory or over budget";
+    case EXACC_ERR_DEVICE: return "device error";
+    case EXACC_ERR_DIVERGED: return "diverged";
+    case EXACC_ERR_UNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+  }
+}
+
+const char* exacc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,336 @@
+// Complex GEMM-like tensor contraction (GETT) on CDNA4 matrix cores.
+//
+// One workgroup (4 waves of 64 lanes) owns a BM x BN tile of C.  Operand
+// tiles of BK = 16 complex columns are staged through LDS as separate real
+// and imaginary planes, k-major, so each 16x16x4 MFMA fragment is read with
+// unit stride.  A complex multiply-add is four real MFMAs (re*re, -im*im,
+// re*im, im*re) into two accumulators.  Global loads for the next k-tile are
+// issued into registers before the MFMAs of the current one (single LDS
+// buffer, register prefetch).  Operand addresses come from the composite
+// (outer, inner) index maps of Gett<R>, so permuted and strided tensors are
+// contracted in place without transposes in HBM.
+#include "common.h"
+
+namespace exacc {
+
+template <typename R>
+struct MF;
+template <>
+struct MF<double> {
+  typedef double4_t acc_t;
+  __device__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator element r of a lane holds row lane/16 + 4r, column lane%16
+  __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct MF<float> {
+  typedef float4_t acc_t;
+  __device__ static acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator element r of a lane holds row 4*(lane/16) + r, column lane%16
+  __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename R>
+struct C2 {
+  R x, y;
+};
+
+__device__ __forceinline__ int64_t cmap(int x, int in, int64_t so, int64_t si) {
+  const int q = x / in;
+  const int r = x - q * in;
+  return (int64_t)q * so + (int64_t)r * si;
+}
+
+template <typename R>
+__device__ __forceinline__ C2<R> ldc(const R* p, int64_t off) {
+  // interleaved complex: one aligned 2-element load
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  v2 t = *reinterpret_cast<const v2*>(p + 2 * off);
+  C2<R> c;
+  c.x = t.x;
+  c.y = t.y;
+  return c;
+}
+
+template <typename R, int BM, int BN, bool AKF, bool BKF, int KIND>
+__global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
+  constexpr int BK = 16;
+  constexpr int LA = BM + 1;  // odd row pitch: conflict-free k-major stores
+  constexpr int LB = BN + 1;
+  constexpr int NA = BM * BK / 256;  // complex elements per thread per tile
+  constexpr int NB = BN * BK / 256;
+  constexpr int TM = BM / 32;  // 16x16 blocks per wave along m
+  constexpr int TN = BN / 32;
+  typedef typename MF<R>::acc_t acc_t;
+
+  __shared__ R sA[2][BK][LA];
+  __shared__ R sB[2][BK][LB];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1;
+
+  const int tiles_m = (g.M + BM - 1) / BM;
+  const int bid = blockIdx.x;
+  const int tm = bid % tiles_m;
+  const int tn = bid / tiles_m;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int64_t batch = blockIdx.y;
+  const R* __restrict__ A = g.A + 2 * batch * g.a_b;
+  const R* __restrict__ B = g.B + 2 * batch * g.b_b;
+
+  // ---- per-thread loader geometry
+  int64_t a_off[AKF ? NA : 1];
+  bool a_ok[AKF ? NA : 1];
+  int a_kk = 0, a_mm = 0, a_kq = 0;
+  if (AKF) {
+    a_kk = tid % BK;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int m = m0 + tid / BK + 16 * q;
+      a_ok[q] = m < g.M;
+      a_off[q] = a_ok[q] ? cmap(m, g.m_in, g.a_mo, g.a_mi) : 0;
+    }
+  } else {
+    a_mm = tid % BM;
+    a_kq = tid / BM;
+    const int m = m0 + a_mm;
+    a_ok[0] = m < g.M;
+    a_off[0] = a_ok[0] ? cmap(m, g.m_in, g.a_mo, g.a_mi) : 0;
+  }
+  int64_t b_off[BKF ? NB : 1];
+  bool b_ok[BKF ? NB : 1];
+  int b_kk = 0, b_nn = 0, b_kq = 0;
+  if (BKF) {
+    b_kk = tid % BK;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int n = n0 + tid / BK + 16 * q;
+      b_ok[q] = n < g.N;
+      b_off[q] = b_ok[q] ? cmap(n, g.n_in, g.b_no, g.b_ni) : 0;
+    }
+  } else {
+    b_nn = tid % BN;
+    b_kq = tid / BN;
+    const int n = n0 + b_nn;
+    b_ok[0] = n < g.N;
+    b_off[0] = b_ok[0] ? cmap(n, g.n_in, g.b_no, g.b_ni) : 0;
+  }
+
+  C2<R> ra[NA], rb[NB];
+  const R sa = g.conj_a ? R(-1) : R(1);
+  const R sb = g.conj_b ? R(-1) : R(1);
+
+  auto load = [&](int k0) {
+    if (AKF) {
+      const int k = k0 + a_kk;
+      const bool kv = k < g.K;
+      const int64_t ko = kv ? cmap(k, g.k_in, g.a_ko, g.a_ki) : 0;
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        if (kv && a_ok[q]) {
+          ra[q] = ldc(A, a_off[q] + ko);
+        } else {
+          ra[q].x = R(0);
+          ra[q].y = R(0);
+        }
+      }
+    } else {
+      constexpr int KS = 256 / BM;
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int k = k0 + a_kq + KS * q;
+        if (k < g.K && a_ok[0]) {
+          ra[q] = ldc(A, a_off[0] + cmap(k, g.k_in, g.a_ko, g.a_ki));
+        } else {
+          ra[q].x = R(0);
+          ra[q].y = R(0);
+        }
+      }
+    }
+    if (BKF) {
+      const int k = k0 + b_kk;
+      const bool kv = k < g.K;
+      const int64_t ko = kv ? cmap(k, g.k_in, g.b_ko, g.b_ki) : 0;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        if (kv && b_ok[q]) {
+          rb[q] = ldc(B, b_off[q] + ko);
+        } else {
+          rb[q].x = R(0);
+          rb[q].y = R(0);
+        }
+      }
+    } else {
+      constexpr int KS = 256 / BN;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int k = k0 + b_kq + KS * q;
+        if (k < g.K && b_ok[0]) {
+          rb[q] = ldc(B, b_off[0] + cmap(k, g.k_in, g.b_ko, g.b_ki));
+        } else {
+          rb[q].x = R(0);
+          rb[q].y = R(0);
+        }
+      }
+    }
+  };
+
+  auto store = [&]() {
+    if (AKF) {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int m = tid / BK + 16 * q;
+        sA[0][a_kk][m] = ra[q].x;
+        sA[1][a_kk][m] = sa * ra[q].y;
+      }
+    } else {
+      constexpr int KS = 256 / BM;
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int k = a_kq + KS * q;
+        sA[0][k][a_mm] = ra[q].x;
+        sA[1][k][a_mm] = sa * ra[q].y;
+      }
+    }
+    if (BKF) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int n = tid / BK + 16 * q;
+        sB[0][b_kk][n] = rb[q].x;
+        sB[1][b_kk][n] = sb * rb[q].y;
+      }
+    } else {
+      constexpr int KS = 256 / BN;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int k = b_kq + KS * q;
+        sB[0][k][b_nn] = rb[q].x;
+        sB[1][k][b_nn] = sb * rb[q].y;
+      }
+    }
+  };
+
+  acc_t accR[TM][TN], accI[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      accR[i][j] = acc_t{0, 0, 0, 0};
+      accI[i][j] = acc_t{0, 0, 0, 0};
+    }
+
+  const int nk = (g.K + BK - 1) / BK;
+  if (nk > 0) {
+    load(0);
+    store();
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int s = 0; s < BK / 4; ++s) {
+      const int kr = 4 * s + (lane >> 4);
+      R ar[TM], ai[TM], br[TN], bi[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int m = wm * (BM / 2) + 16 * i + (lane & 15);
+        ar[i] = sA[0][kr][m];
+        ai[i] = sA[1][kr][m];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = wn * (BN / 2) + 16 * j + (lane & 15);
+        br[j] = sB[0][kr][n];
+        bi[j] = sB[1][kr][n];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          accR[i][j] = MF<R>::mma(ar[i], br[j], accR[i][j]);
+          accR[i][j] = MF<R>::mma(-ai[i], bi[j], accR[i][j]);
+          accI[i][j] = MF<R>::mma(ar[i], bi[j], accI[i][j]);
+          accI[i][j] = MF<R>::mma(ai[i], br[j], accI[i][j]);
+        }
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      store();
+      __syncthreads();
+    }
+  }
+
+  // ---- epilogue (output layout of the 16x16 block per MF<R>::row)
+  R* __restrict__ Cb = g.C + 2 * batch * g.c_b;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn * (BN / 2) + 16 * j + (lane & 15);
+      if (col >= g.N) continue;
+      const int64_t co = cmap(col, g.n_in, g.c_no, g.c_ni);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * (BM / 2) + 16 * i + MF<R>::row(lane, r);
+        if (row >= g.M) continue;
+        const int64_t off = 2 * (co + cmap(row, g.m_in, g.c_mo, g.c_mi));
+        const R xr = accR[i][j][r], xi = accI[i][j][r];
+        R yr = g.alpha_re * xr - g.alpha_im * xi;
+        R yi = g.alpha_re * xi + g.alpha_im * xr;
+        if (g.accumulate) {
+          yr += Cb[off];
+          yi += Cb[off + 1];
+        }
+        Cb[off] = yr;
+        Cb[off + 1] = yi;
+      }
+    }
+}
+
+template <typename R, int BM, int BN, int KIND>
+static void launch_cfg(const Gett<R>& g, hipStream_t s) {
+  const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  const bool akf = (g.a_ki == 1) || !(g.a_mi == 1);
+  const bool bkf = (g.b_ki == 1) || !(g.b_ni == 1);
+  for (int64_t b0 = 0; b0 < g.nbatch; b0 += 65535) {
+    Gett<R> h = g;
+    const int nb = (int)((g.nbatch - b0) < 65535 ? (g.nbatch - b0) : 65535);
+    h.A = g.A + 2 * b0 * g.a_b;
+    h.B = g.B + 2 * b0 * g.b_b;
+    h.C = g.C + 2 * b0 * g.c_b;
+    dim3 grid(tiles, nb), block(256);
+    if (akf && bkf)
+      hipLaunchKernelGGL((gett_kernel<R, BM, BN, true, true, KIND>), grid, block, 0, s, h);
+    else if (akf)
+      hipLaunchKernelGGL((gett_kernel<R, BM, BN, true, false, KIND>), grid, block, 0, s, h);
+    else if (bkf)
+      hipLaunchKernelGGL((gett_kernel<R, BM, BN, false, true, KIND>), grid, block, 0, s, h);
+    else
+      hipLaunchKernelGGL((gett_kernel<R, BM, BN, false, false, KIND>), grid, block, 0, s, h);
+    HIPCHECK(hipGetLastError());
+  }
+}
+
+template <typename R>
+void launch_gett(const Gett<R>& g, int kind, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return;
+  if ((int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) > 0x7fffffffLL)
+    raise(-1, "contraction too large for one launch");
+  switch (kind) {
+    case GETT_LADDER_BUILD: launch_cfg<R, 64, 64, GETT_LADDER_BUILD>(g, s); break;
+    case GETT_LADDER_CONTRACT: launch_cfg<R, 64, 64, GETT_LADDER_CONTRACT>(g, s); break;
+    case GETT_RING: launch_cfg<R, 64, 64, GETT_RING>(g, s); break;
+    default: launch_cfg<R, 64, 64, GETT_GENERIC>(g, s); break;
+  }
+}
+
+template void launch_gett<double>(const Gett<double>&, int, hipStream_t);
+template void launch_gett<float>(const Gett<float>&, int, hipStream_t);
+
+}  // namespace exacc

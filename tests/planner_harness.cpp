@@ -1,0 +1,277 @@
+// CPU check of the contraction planner (einsum.cpp): launch_gett is replaced by
+// a CPU loop with the same semantics, every spec the iteration issues is run
+// on small ragged shapes, and the result is compared with a direct loop over
+// all label values.  Also checks that every GETT offset stays inside its view.
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "einsum.h"
+
+namespace exacc {
+void raise(int status, const std::string& msg) { throw Error{status, msg}; }
+void hip_check(hipError_t, const char*, const char*, int) {}
+
+struct Span {
+  const double* lo;
+  const double* hi;
+};
+static std::vector<Span> g_spans;
+static int g_bad = 0;
+static long g_launches = 0;
+
+static void chk(const double* p) {
+  for (auto& s : g_spans)
+    if (p >= s.lo && p + 1 < s.hi) return;
+  g_bad++;
+}
+
+static int64_t cm(int x, int in, int64_t so, int64_t si) { return (int64_t)(x / in) * so + (int64_t)(x % in) * si; }
+
+template <typename R>
+void launch_gett(const Gett<R>& g, int, hipStream_t) {
+  g_launches++;
+  for (int b = 0; b < g.nbatch; ++b)
+    for (int m = 0; m < g.M; ++m)
+      for (int n = 0; n < g.N; ++n) {
+        std::complex<double> acc = 0;
+        for (int k = 0; k < g.K; ++k) {
+          const R* a = g.A + 2 * (b * g.a_b + cm(m, g.m_in, g.a_mo, g.a_mi) + cm(k, g.k_in, g.a_ko, g.a_ki));
+          const R* bb = g.B + 2 * (b * g.b_b + cm(k, g.k_in, g.b_ko, g.b_ki) + cm(n, g.n_in, g.b_no, g.b_ni));
+          chk((const double*)a);
+          chk((const double*)bb);
+          std::complex<double> x(a[0], g.conj_a ? -a[1] : a[1]), y(bb[0], g.conj_b ? -bb[1] : bb[1]);
+          acc += x * y;
+        }
+        R* c = g.C + 2 * (b * g.c_b + cm(m, g.m_in, g.c_mo, g.c_mi) + cm(n, g.n_in, g.c_no, g.c_ni));
+        chk((const double*)c);
+        std::complex<double> r = std::complex<double>(g.alpha_re, g.alpha_im) * acc;
+        if (g.accumulate) r += std::complex<double>(c[0], c[1]);
+        c[0] = r.real();
+        c[1] = r.imag();
+      }
+}
+template void launch_gett<double>(const Gett<double>&, int, hipStream_t);
+template void launch_gett<float>(const Gett<float>&, int, hipStream_t);
+}  // namespace exacc
+
+using namespace exacc;
+typedef std::complex<double> zc;
+
+struct Buf {
+  std::vector<double> d;
+  explicit Buf(int64_t n) : d(2 * n) {}
+  double* p() { return d.data(); }
+};
+
+static std::mt19937_64 rng(12345);
+static void fill(Buf& b) {
+  std::normal_distribution<double> nd;
+  for (auto& x : b.d) x = nd(rng);
+}
+
+// direct evaluation of C = alpha * sum A B (+ C)
+static void naive(const std::string& spec, zc alpha, const TV<double>& A, const TV<double>& B, bool acc,
+                  const TV<double>& C) {
+  double* out = C.p;
+  const size_t comma = spec.find(','), arrow = spec.find("->");
+  const std::string la = spec.substr(0, comma), lb = spec.substr(comma + 1, arrow - comma - 1),
+                    lc = spec.substr(arrow + 2);
+  std::string labels;
+  std::map<char, int64_t> dim;
+  auto reg = [&](const std::string& l, const TV<double>& t) {
+    for (int i = 0; i < t.nd; ++i) {
+      if (labels.find(l[i]) == std::string::npos) labels.push_back(l[i]);
+      dim[l[i]] = t.dim[i];
+    }
+  };
+  reg(la, A);
+  reg(lb, B);
+  reg(lc, C);
+  auto off = [&](const std::string& l, const TV<double>& t, const std::map<char, int64_t>& v) {
+    int64_t o = 0;
+    for (int i = 0; i < t.nd; ++i) o += v.at(l[i]) * t.str[i];
+    return o;
+  };
+  // zero or keep C over its own index space
+  std::map<char, int64_t> val;
+  for (char c : labels) val[c] = 0;
+  std::vector<zc> accum;
+  // enumerate C index space
+  int64_t ctot = 1;
+  for (int i = 0; i < C.nd; ++i) ctot *= C.dim[i];
+  for (int64_t q = 0; q < ctot; ++q) {
+    int64_t r = q;
+    for (int i = C.nd - 1; i >= 0; --i) {
+      val[lc[i]] = r % C.dim[i];
+      r /= C.dim[i];
+    }
+    const int64_t o = off(lc, C, val);
+    if (!acc) {
+      out[2 * o] = 0;
+      out[2 * o + 1] = 0;
+    }
+  }
+  int64_t tot = 1;
+  for (char c : labels) tot *= dim[c];
+  for (int64_t q = 0; q < tot; ++q) {
+    int64_t r = q;
+    for (int i = (int)labels.size() - 1; i >= 0; --i) {
+      val[labels[i]] = r % dim[labels[i]];
+      r /= dim[labels[i]];
+    }
+    const double* a = A.p + 2 * off(la, A, val);
+    const double* b = B.p + 2 * off(lb, B, val);
+    zc x(a[0], A.conj ? -a[1] : a[1]), y(b[0], B.conj ? -b[1] : b[1]);
+    const int64_t o = off(lc, C, val);
+    zc z = alpha * x * y;
+    out[2 * o] += z.real();
+    out[2 * o + 1] += z.imag();
+  }
+}
+
+int main() {
+  int fails = 0, cases = 0;
+  const int o = 3, v = 5, X = 4, n = o + v;
+  const int64_t nX = (int64_t)n * X, Po = o * (o - 1) / 2, Pv = v * (v - 1) / 2;
+  Buf Bt(n * nX);
+  fill(Bt);
+  TV<double> Boo = sview(Bt.p(), {o, o, X}, {nX, X, 1});
+  TV<double> Bov = sview(Bt.p() + 2 * (int64_t)o * X, {o, v, X}, {nX, X, 1});
+  TV<double> Bvo = sview(Bt.p() + 2 * (int64_t)o * nX, {v, o, X}, {nX, X, 1});
+  TV<double> Bvv = sview(Bt.p() + 2 * ((int64_t)o * nX + (int64_t)o * X), {v, v, X}, {nX, X, 1});
+  std::vector<Buf*> pool;
+  auto mk = [&](std::initializer_list<int64_t> dims) {
+    int64_t t = 1;
+    for (auto d : dims) t *= d;
+    Buf* b = new Buf(t);
+    fill(*b);
+    pool.push_back(b);
+    return view(b->p(), dims);
+  };
+  auto run = [&](const char* spec, zc alpha, TV<double> A, TV<double> B, bool acc, TV<double> C) {
+    cases++;
+    g_spans.clear();
+    auto add = [&](const double* base, int64_t ncplx) { g_spans.push_back({base, base + 2 * ncplx}); };
+    add(Bt.p(), n * nX);
+    for (auto* b : pool) add(b->p(), (int64_t)b->d.size() / 2);
+    // reference on a copy of C's whole buffer
+    Buf* owner = nullptr;
+    for (auto* b : pool)
+      if (C.p >= b->p() && C.p < b->p() + b->d.size()) owner = b;
+    std::vector<double> before = owner->d;
+    std::vector<double> ref = owner->d;
+    const int64_t shift = C.p - owner->p();
+    TV<double> Cr = C;
+    Cr.p = ref.data() + shift;
+    naive(spec, alpha, A, B, acc, Cr);
+    const int bad0 = g_bad;
+    try {
+      contract(nullptr, spec, cplx{alpha.real(), alpha.imag()}, A, B, acc, C);
+    } catch (const Error& e) {
+      printf("FAIL %s: planner raised: %s\n", spec, e.msg.c_str());
+      fails++;
+      return;
+    }
+    double err = 0, mx = 0;
+    for (size_t i = 0; i < ref.size(); ++i) {
+      err = std::max(err, std::fabs(ref[i] - owner->d[i]));
+      mx = std::max(mx, std::fabs(ref[i]));
+    }
+    const bool ok = err <= 1e-12 * std::max(1.0, mx) && g_bad == bad0;
+    if (!ok) {
+      printf("FAIL %s: max err %.3e (scale %.3e), out-of-view accesses %d\n", spec, err, mx, g_bad - bad0);
+      fails++;
+    }
+    (void)before;
+  };
+  const zc ONE(1, 0), MONE(-1, 0), HALF(0.5, 0), CPX(0.3, -0.7);
+  // integral classes
+  run("kiP,ljP->klij", ONE, Boo, Boo, false, mk({o, o, o, o}));
+  run("kjP,liP->klij", MONE, Boo, Boo, true, mk({o, o, o, o}));
+  run("kiP,lcP->klic", ONE, Boo, Bov, false, mk({o, o, o, v}));
+  run("kcP,liP->klic", MONE, Bov, Boo, true, mk({o, o, o, v}));
+  run("kcP,ldP->klcd", ONE, Bov, Bov, false, mk({o, o, v, v}));
+  run("kdP,lcP->klcd", MONE, Bov, Bov, true, mk({o, o, v, v}));
+  run("acP,kiP->aikc", ONE, Bvv, Boo, false, mk({v, o, o, v}));
+  run("aiP,kcP->aikc", MONE, Bvo, Bov, true, mk({v, o, o, v}));
+  {
+    const int nb = 2, b0 = 2;
+    auto Bc = sview(Bvv.p + 2 * (int64_t)b0 * nX, {nb, v, X}, {nX, X, 1});
+    auto tmp = mk({nb, o, v, v});
+    run("bcP,kdP->bkcd", ONE, Bc, Bov, false, tmp);
+    run("bdP,kcP->bkcd", MONE, Bc, Bov, true, tmp);
+  }
+  // iteration
+  auto t1 = mk({o, v});
+  auto T2 = mk({o, o, v, v}), TAU = mk({o, o, v, v});
+  auto taup = mk({Po, Pv});
+  auto Voovv = mk({o, o, v, v}), Vooov = mk({o, o, o, v}), Vvovo = mk({v, o, o, v});
+  auto Hac = mk({v, v}), Gac = mk({v, v}), Hki = mk({o, o}), Gki = mk({o, o}), Hkc = mk({o, v});
+  run("klcd,klda->ac", HALF, Voovv, TAU, false, Hac);
+  run("klcd,licd->ki", HALF, Voovv, TAU, false, Hki);
+  run("klcd,ld->kc", ONE, Voovv, t1, false, Hkc);
+  auto y = mk({X});
+  run("kdP,kd->P", ONE, Bov, t1, false, y);
+  run("acP,P->ac", ONE, Bvv, y, true, Gac);
+  auto Zt = mk({v, v, X});
+  run("kd,kcP->dcP", ONE, t1, Bov, false, Zt);
+  run("adP,dcP->ac", MONE, Bvv, Zt, true, Gac);
+  run("klic,lc->ki", MONE, Vooov, t1, true, Gki);
+  auto H4 = mk({v, o, o, v}), U = mk({o, o, X}), Vt = mk({v, o, X});
+  run("kdP,id->kiP", ONE, Bov, t1, false, U);
+  run("acP,ic->aiP", ONE, Bvv, t1, false, Vt);
+  run("acP,kiP->aikc", ONE, Bvv, U, true, H4);
+  run("aiP,kcP->aikc", MONE, Vt, Bov, true, H4);
+  run("klic,la->aikc", MONE, Vooov, t1, true, H4);
+  run("aild,klcd->aikc", ONE, mk({v, o, o, v}), Voovv, true, H4);
+  auto R = mk({o, o, v, v});
+  run("aikc,bjkc->ijab", ONE, H4, mk({v, o, o, v}), false, R);
+  run("aiP,bjP->ijab", ONE, Vt, Bvo, true, R);
+  auto Zij = mk({o, o, v, v}), Zab = mk({o, o, v, v});
+  run("kj,ikab->ijab", ONE, Gki, T2, false, Zij);
+  run("ac,ijcb->ijab", ONE, Gac, T2, false, Zab);
+  auto Cp = mk({Po, v, o}), Cf = mk({o, o, v, o});
+  run("bkx,px->pbk", MONE, mk({v, o, Pv}), taup, false, Cp);
+  run("bikc,jc->ijbk", ONE, Vvovo, t1, true, Cf);
+  run("bjkc,ic->ijbk", MONE, Vvovo, t1, true, Cf);
+  run("ijak,kb->ijab", ONE, Cf, t1, true, Zab);
+  auto Af = mk({o, o, o, o});
+  run("klic,jc->klij", ONE, Vooov, t1, true, Af);
+  run("kljc,ic->klij", MONE, Vooov, t1, true, Af);
+  run("klcd,ijcd->klij", HALF, Voovv, TAU, true, Af);
+  auto Znp = mk({Po, Pv});
+  run("qp,qx->px", ONE, mk({Po, Po}), taup, false, Znp);
+  {
+    const int a = 1, nb = v - a - 1;
+    auto Ba = sview(Bvv.p + 2 * (int64_t)a * nX, {v, X}, {X, 1});
+    auto Bb = sview(Bvv.p + 2 * (int64_t)(a + 1) * nX, {nb, v, X}, {nX, X, 1});
+    run("cP,bdP->cbd", ONE, Ba, Bb, false, mk({v, nb, v}));
+    const int64_t rows = 4, start = 3;
+    auto W = mk({rows, Pv});
+    auto Zc = sview(Znp.p + 2 * start, {Po, rows}, {Pv, 1});
+    run("py,xy->px", ONE, taup, W, true, Zc);
+  }
+  auto S1 = mk({o, v}), M1 = mk({o, o}), Y = mk({o, v, X});
+  run("ac,ic->ia", ONE, Hac, t1, false, S1);
+  run("ki,ka->ia", ONE, Hki, t1, true, S1);
+  run("kc,ikac->ia", ONE, Hkc, T2, true, S1);
+  run("kc,ic->ki", ONE, Hkc, t1, false, M1);
+  run("ki,ka->ia", ONE, M1, t1, true, S1);
+  run("ikcd,kdP->icP", ONE, TAU, Bov, false, Y);
+  run("icP,acP->ia", ONE, Y, Bvv, true, S1);
+  run("klic,klca->ia", HALF, Vooov, TAU, true, S1);
+  run("aikc,kc->ia", MONE, Vvovo, t1, true, S1);
+  // generic: conjugation, complex alpha, batch labels, empty sum
+  run("zmk,zkn->zmn", CPX, conj(mk({3, 4, 5})), mk({3, 5, 6}), false, mk({3, 4, 6}));
+  run("mk,kn->nm", CPX, mk({7, 2}), conj(mk({2, 9})), true, mk({9, 7}));
+  run("mk,kn->mn", ONE, mk({3, 0}), mk({0, 4}), false, mk({3, 4}));
+  printf("%d cases, %d failures, %ld launches\n", cases, fails, g_launches);
+  for (auto* b : pool) delete b;
+  return fails ? 1 : 0;
+}

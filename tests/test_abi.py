@@ -1,0 +1,39 @@
+"""The C-ABI library loads and exports every symbol include/exacc.h declares (no GPU calls)."""
+import ctypes
+
+from paper_2103_08473_amd import exacc
+
+
+def test_library_exports_every_declared_symbol():
+    L = exacc.load()
+    names = exacc.declared_symbols()
+    assert "exacc_ccsd_create" in names and "exacc_ccsd_iterate" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_host_only_entry_points():
+    """Functions that never touch the device: options, memory plan, flop count, status text."""
+    o = exacc.default_opts()
+    assert o.diis_size == 8 and o.max_iter == 30 and abs(o.tol - 1e-9) < 1e-24
+    assert o.precision == exacc.FP64 and o.level_shift == 0.0
+    m1 = exacc.memory_estimate(10, 40, 120)
+    m2 = exacc.memory_estimate(40, 360, 1200)
+    assert 0 < m1 < m2
+    assert exacc.memory_estimate(0, 40, 120) == 0
+    # ladder flops: 8 * (2 X Pv^2 + Po Pv^2)
+    Po, Pv = 40 * 39 / 2, 360 * 359 / 2
+    assert abs(exacc.ladder_flops(40, 360, 1200) - 8 * (2 * 1200 * Pv ** 2 + Po * Pv ** 2)) < 1e3
+    L = exacc.load()
+    assert L.exacc_status_string(0) == b"ok"
+    assert L.exacc_status_string(-2).startswith(b"out of device memory")
+    assert L.exacc_ccsd_destroy(None) == 0
+
+
+def test_create_rejects_bad_sizes_before_touching_the_device():
+    L = exacc.load()
+    h = ctypes.c_void_p()
+    o = exacc.default_opts()
+    assert L.exacc_ccsd_create(ctypes.byref(h), 0, 10, 10, None, None, ctypes.byref(o)) == -1
+    assert not h.value
+    assert b"nocc" in L.exacc_last_error()
