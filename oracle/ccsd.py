@@ -60,6 +60,14 @@ def build_integrals(B, nocc):
     }
 
 
+def ladder_rows(B, o, tau_, a0, a1):
+    """Rows a0 <= a < a1 of the particle ladder 1/2 sum_cd V^{ab}_{cd} tau_ij^cd,
+    with <ab||cd> formed from B for those rows; returns [i, j, a-a0, b]."""
+    n = B.shape[1]
+    vabcd = antisym(B, slice(o + a0, o + a1), slice(o, n), slice(o, n), slice(o, n))
+    return 0.5 * np.einsum('abcd,ijcd->ijab', vabcd, tau_, optimize=True)
+
+
 def _ladder(ints, tau_):
     """1/2 sum_cd V^{ab}_{cd} tau_ij^cd with <ab||cd> formed for blocks of a."""
     B, o = ints['B'], ints['o']
@@ -69,8 +77,7 @@ def _ladder(ints, tau_):
     blk = max(1, int(_LADDER_BLOCK_BYTES // (16 * v ** 3)))
     for a0 in range(0, v, blk):
         a1 = min(v, a0 + blk)
-        vabcd = antisym(B, slice(o + a0, o + a1), slice(o, n), slice(o, n), slice(o, n))
-        out[:, :, a0:a1, :] = 0.5 * np.einsum('abcd,ijcd->ijab', vabcd, tau_, optimize=True)
+        out[:, :, a0:a1, :] = ladder_rows(B, o, tau_, a0, a1)
     return out
 
 
