@@ -44,7 +44,12 @@ struct Gett {
   const R* A;  // interleaved complex
   const R* B;
   R* C;
+  int kslice;  // split-K: workgroup z covers k in [z*kslice, min(K, (z+1)*kslice))
+  R* ws;       // split-K partial sums [z][batch][m][n] (unscaled)
 };
+
+// Scratch the calling thread's GETT launches may use for split-K partials.
+void set_gett_workspace(void* p, size_t bytes);
 
 enum GettKind { GETT_GENERIC = 0, GETT_LADDER_BUILD = 1, GETT_LADDER_CONTRACT = 2, GETT_RING = 3 };
 

@@ -101,6 +101,7 @@ static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
                    p.Po * v * o + oo * v * o + oo * oo + p.Po * p.Po);
   add("Ta", (int64_t)v * std::max(1, v - 1) * v);
   add("W", p.chunk_pairs * std::max<int64_t>(1, p.Pv));
+  add("splitk_ws", (256ll << 20) / 16);
   add("Braw", n * n * X, true);
   add("vovv_tmp", p.vovv_chunk * vovv_row, true);
   size_t pers = 0, tr = 0;
@@ -175,7 +176,12 @@ struct Handle {
     for (auto e : tm.pool) (void)hipEventDestroy(e);
     if (own_stream && s) (void)hipStreamDestroy(s);
   }
-  void use() { set_alloc_registry(ranges.data(), (int)ranges.size()); }
+  void* ws = nullptr;  // split-K scratch
+  size_t ws_bytes = 0;
+  void use() {
+    set_alloc_registry(ranges.data(), (int)ranges.size());
+    set_gett_workspace(ws, ws_bytes);
+  }
   double* dalloc(int64_t complex_elems) {
     void* p = nullptr;
     const size_t b = (size_t)std::max<int64_t>(complex_elems, 1) * 16;
@@ -643,6 +649,8 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
     h->eps = (double*)h->dalloc((n + 1) / 2);
     HIPCHECK(hipMemcpyAsync(h->eps, eh.data(), n * sizeof(double), hipMemcpyHostToDevice, h->s));
     h->red = h->dalloc(65536);
+    h->ws_bytes = (size_t)256 << 20;
+    h->ws = h->dalloc((int64_t)(h->ws_bytes / 16));
     h->redout = h->dalloc(64);
     // B: stage raw, check Hermiticity and finiteness on the device, transpose to [p][q][P]
     const double* Braw = B;
@@ -738,6 +746,7 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
   } catch (...) {
     if (h->s) (void)hipStreamSynchronize(h->s);
     set_alloc_registry(nullptr, 0);
+    set_gett_workspace(nullptr, 0);
     delete h;
     throw;
   }
@@ -932,6 +941,7 @@ int exacc_ccsd_destroy(exacc_ccsd_t hh) {
     Handle* h = reinterpret_cast<Handle*>(hh);
     if (h->s) (void)hipStreamSynchronize(h->s);
     set_alloc_registry(nullptr, 0);
+    set_gett_workspace(nullptr, 0);
     delete h;
     return (int)EXACC_OK;
   });

@@ -84,6 +84,9 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
   const R* __restrict__ A = g.A + 2 * batch * g.a_b;
   const R* __restrict__ B = g.B + 2 * batch * g.b_b;
 
+  const int kb = blockIdx.z * g.kslice;
+  const int ke = (g.K - kb) < g.kslice ? g.K : kb + g.kslice;
+
   // ---- per-thread loader geometry
   int64_t a_off[AKF ? NA : 1];
   bool a_ok[AKF ? NA : 1];
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
   auto load = [&](int k0) {
     if (AKF) {
       const int k = k0 + a_kk;
-      const bool kv = k < g.K;
+      const bool kv = k < ke;
       const int64_t ko = kv ? cmap(k, g.k_in, g.a_ko, g.a_ki) : 0;
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
         const int k = k0 + a_kq + KS * q;
-        if (k < g.K && a_ok[0]) {
+        if (k < ke && a_ok[0]) {
           ra[q] = ldc(A, a_off[0] + cmap(k, g.k_in, g.a_ko, g.a_ki));
         } else {
           ra[q].x = R(0);
@@ -155,7 +158,7 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
     }
     if (BKF) {
       const int k = k0 + b_kk;
-      const bool kv = k < g.K;
+      const bool kv = k < ke;
       const int64_t ko = kv ? cmap(k, g.k_in, g.b_ko, g.b_ki) : 0;
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
@@ -171,7 +174,7 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const int k = k0 + b_kq + KS * q;
-        if (k < g.K && b_ok[0]) {
+        if (k < ke && b_ok[0]) {
           rb[q] = ldc(B, b_off[0] + cmap(k, g.k_in, g.b_ko, g.b_ki));
         } else {
           rb[q].x = R(0);
@@ -225,14 +228,14 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
       accI[i][j] = acc_t{0, 0, 0, 0};
     }
 
-  const int nk = (g.K + BK - 1) / BK;
+  const int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
   if (nk > 0) {
-    load(0);
+    load(kb);
     store();
   }
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) load((kt + 1) * BK);
+    if (kt + 1 < nk) load(kb + (kt + 1) * BK);
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
       const int kr = 4 * s + (lane >> 4);
@@ -268,6 +271,25 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
 
   // ---- epilogue (output layout of the 16x16 block per MF<R>::row)
   R* __restrict__ Cb = g.C + 2 * batch * g.c_b;
+  if (gridDim.z > 1) {  // split-K: raw partial sums, reduced by gett_splitk_reduce
+    R* __restrict__ W = g.ws + 2 * (((int64_t)blockIdx.z * gridDim.y + batch) * g.M) * g.N;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = n0 + wn * (BN / 2) + 16 * j + (lane & 15);
+        if (col >= g.N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * (BM / 2) + 16 * i + MF<R>::row(lane, r);
+          if (row >= g.M) continue;
+          const int64_t off = 2 * ((int64_t)row * g.N + col);
+          W[off] = accR[i][j][r];
+          W[off + 1] = accI[i][j][r];
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -293,6 +315,38 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
     }
 }
 
+// C[b](m, n) = alpha * sum_z ws[z][b][m][n] (+ C), fixed summation order.
+template <typename R>
+__global__ __launch_bounds__(256) void gett_splitk_reduce(Gett<R> g, int nz, int nb) {
+  const int64_t MN = (int64_t)g.M * g.N, tot = MN * nb;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < tot; t += (int64_t)gridDim.x * 256) {
+    const int64_t b = t / MN, mn = t - b * MN;
+    const int m = (int)(mn / g.N), n = (int)(mn - (int64_t)m * g.N);
+    R sr = 0, si = 0;
+    for (int z = 0; z < nz; ++z) {
+      const R* w = g.ws + 2 * (((int64_t)z * nb + b) * MN + mn);
+      sr += w[0];
+      si += w[1];
+    }
+    R* c = g.C + 2 * (b * g.c_b + cmap(m, g.m_in, g.c_mo, g.c_mi) + cmap(n, g.n_in, g.c_no, g.c_ni));
+    R yr = g.alpha_re * sr - g.alpha_im * si;
+    R yi = g.alpha_re * si + g.alpha_im * sr;
+    if (g.accumulate) {
+      yr += c[0];
+      yi += c[1];
+    }
+    c[0] = yr;
+    c[1] = yi;
+  }
+}
+
+static thread_local void* g_ws = nullptr;
+static thread_local size_t g_ws_bytes = 0;
+void set_gett_workspace(void* p, size_t bytes) {
+  g_ws = p;
+  g_ws_bytes = bytes;
+}
+
 template <typename R, int BM, int BN, int KIND>
 static void launch_cfg(const Gett<R>& g, hipStream_t s) {
   const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
@@ -304,7 +358,26 @@ static void launch_cfg(const Gett<R>& g, hipStream_t s) {
     h.A = g.A + 2 * b0 * g.a_b;
     h.B = g.B + 2 * b0 * g.b_b;
     h.C = g.C + 2 * b0 * g.c_b;
-    dim3 grid(tiles, nb), block(256);
+    // split K when the output alone gives too few workgroups to fill the chip
+    int nz = 1;
+    h.kslice = g.K > 0 ? g.K : 1;
+    const int64_t wgs = (int64_t)tiles * nb;
+    if (g_ws && wgs < 1024 && g.K >= 1024) {
+      int64_t want = (1024 + wgs - 1) / wgs;
+      want = want < (g.K + 255) / 256 ? want : (g.K + 255) / 256;  // >= 256 k per slice
+      const int64_t per = (int64_t)g.M * g.N * nb * 2 * (int64_t)sizeof(R);
+      const int64_t cap = per > 0 ? (int64_t)(g_ws_bytes / per) : 0;
+      if (want > cap) want = cap;
+      if (want > 1024) want = 1024;
+      if (want >= 2) {
+        int64_t ks = (g.K + want - 1) / want;
+        ks = (ks + 15) / 16 * 16;
+        nz = (int)((g.K + ks - 1) / ks);
+        h.kslice = (int)ks;
+        h.ws = (R*)g_ws;
+      }
+    }
+    dim3 grid(tiles, nb, nz), block(256);
     if (akf && bkf)
       hipLaunchKernelGGL((gett_kernel<R, BM, BN, true, true, KIND>), grid, block, 0, s, h);
     else if (akf)
@@ -314,6 +387,13 @@ static void launch_cfg(const Gett<R>& g, hipStream_t s) {
     else
       hipLaunchKernelGGL((gett_kernel<R, BM, BN, false, false, KIND>), grid, block, 0, s, h);
     HIPCHECK(hipGetLastError());
+    if (nz > 1) {
+      const int64_t tot = (int64_t)g.M * g.N * nb;
+      int64_t blocks = (tot + 255) / 256;
+      if (blocks > 65535 * 8) blocks = 65535 * 8;
+      hipLaunchKernelGGL(gett_splitk_reduce<R>, dim3((unsigned)blocks), dim3(256), 0, s, h, nz, nb);
+      HIPCHECK(hipGetLastError());
+    }
   }
 }
 
