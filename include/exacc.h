@@ -49,13 +49,14 @@ enum { EXACC_FP64 = 0, EXACC_MIXED_FP32 = 1, EXACC_MIXED_BF16X3 = 2 };
 /* Options; the keywords are the paper's input keywords (Supporting
  * Information, table of ExaCorr keywords) where one exists. */
 typedef struct {
-  int    precision;          /* EXACC_FP64 (default) */
+  int    precision;          /* EXACC_FP64 (default) or EXACC_MIXED_FP32 */
   int    diis_size;          /* Pulay subspace size, default 8; 0 = plain Jacobi steps */
   int    max_iter;           /* .NCYCLES, default 30 */
   double tol;                /* .TCONVERG, default 1e-9, on ||Delta||_2 over the unique amplitudes */
   double level_shift;        /* .LSHIFT, default 0: added to every virtual energy in the denominators */
   int    fp64_final_iters;   /* mixed precision: at least this many FP64 iterations at the end (default 3) */
-  double mixed_switch_tol;   /* mixed precision: FP64 contractions once ||Delta|| < this (default 1e-5) */
+  double mixed_switch_tol;   /* mixed precision: FP64 contractions once ||Delta|| < this (default 1e-5);
+                                the DIIS subspace restarts at the switch.  Converged requires FP64 */
   int    inputs_on_device;   /* 0: eps and B passed to create are host pointers; 1: device pointers */
   void*  stream;             /* hipStream_t to enqueue on; NULL: the handle creates its own */
   size_t hbm_budget_bytes;   /* 0 = unlimited; create fails with EXACC_ERR_NOMEM above it */
@@ -108,7 +109,9 @@ int exacc_ccsd_set_amplitudes(exacc_ccsd_t h, const double* t1, const double* t2
 
 /* The residual of eq. CC_general at the current amplitudes, without updating
  * them: s1 [nocc][nvir], s2 [nocc][nocc][nvir][nvir] (full, antisymmetric),
- * both including the diagonal Fock part.  Either may be NULL. */
+ * both including the diagonal Fock part.  Either may be NULL.  Contractions
+ * run in the precision of the current phase (see exacc_ccsd_phase); the sum
+ * with the driver and the diagonal part is formed in FP64. */
 int exacc_ccsd_residual(exacc_ccsd_t h, double* s1, double* s2, int ptr_on_device);
 
 /* Accumulated device time in ms of each stage since create (or the last
@@ -116,6 +119,11 @@ int exacc_ccsd_residual(exacc_ccsd_t h, double* s1, double* s2, int ptr_on_devic
  * opts.timing = 1.  names[k] (static strings) and ms[k] for k < *count.
  * Pass reset = 1 to zero the counters after reading. */
 int exacc_ccsd_stage_times(exacc_ccsd_t h, const char** names, double* ms, int* count, int reset);
+
+/* Precision of the contractions the next iterate() step will use: 1 = FP32
+ * (mixed-precision phase), 0 = FP64.  *fp64_iters (may be NULL) receives the
+ * number of FP64 iterations since the switch. */
+int exacc_ccsd_phase(exacc_ccsd_t h, int* fp32, int* fp64_iters);
 
 /* Algorithmic flop count (real flops, 8 per complex multiply-add) of one
  * iteration's particle-particle ladder: tile build 2*naux*P_v^2 plus

@@ -62,21 +62,29 @@ void launch_gett(const Gett<R>& g, int kind, hipStream_t s);
 // ---------------------------------------------------------------------------
 void k_transpose_B(const double* B, double* Bt, int64_t X, int64_t nn, hipStream_t s);
 void k_check_B(const double* B, int64_t X, int n, double* out3, double* scratch, hipStream_t s);
-void k_pack_last2(double* out, const double* in, const int* rowmap, int64_t rows, int m,
-                  int64_t in_row_stride, hipStream_t s);
-void k_unpack_tau(const double* t1, const double* t2p, double* T2, double* TAU, double* taup,
-                  int o, int v, hipStream_t s);
-void k_ring_operands(const double* T2, const double* t1, double* Tq, double* Xp, int o, int v,
-                     hipStream_t s);
-void k_expand_c(const double* Vooov, const double* Cp, double* Cf, int o, int v, hipStream_t s);
-void k_ladder_antisym(const double* Ta, double* W, int nb, int v, hipStream_t s);
-void k_assemble_t2(const double* Znp, const double* Zab, const double* Zij, const double* R,
-                   const double* Voovv_p, const double* t2p, const double* eps, int o, int v,
-                   double shift, double* xt, double* e, double* s2_full, double* partial,
-                   int nblk, hipStream_t s);
-void k_assemble_t1(const double* S1, const double* t1, const double* eps, int o, int v,
-                   double shift, double* xt, double* e, double* s1_full, double* partial,
-                   hipStream_t s);
+template <typename T>
+void k_pack_last2(T* out, const T* in, const int* rowmap, int64_t rows, int m, int64_t in_row_stride,
+                  hipStream_t s);
+template <typename T>
+void k_unpack_tau(const double* t1, const double* t2p, T* T2, T* TAU, T* taup, int o, int v,
+                  hipStream_t s);
+template <typename T>
+void k_ring_operands(const T* T2, const double* t1, T* Tq, T* Xp, int o, int v, hipStream_t s);
+template <typename T>
+void k_expand_c(const T* Vooov, const T* Cp, T* Cf, int o, int v, hipStream_t s);
+template <typename T>
+void k_ladder_antisym(const T* Ta, T* W, int nb, int v, hipStream_t s);
+// S2 pieces of type T are summed in FP64 with the FP64 driver <ab||ij> and the
+// diagonal Fock part; writes the Jacobi step (or the full residual into s2_full).
+template <typename T>
+void k_assemble_t2(const T* Znp, const T* Zab, const T* Zij, const T* R, const double* Voovv_p,
+                   const double* t2p, const double* eps, int o, int v, double shift, double* xt,
+                   double* e, double* s2_full, double* partial, int nblk, hipStream_t s);
+template <typename T>
+void k_assemble_t1(const T* S1, const double* t1, const double* eps, int o, int v, double shift,
+                   double* xt, double* e, double* s1_full, double* partial, hipStream_t s);
+// FP64 -> FP32, round to nearest even, nreal reals
+void k_cast(const double* in, float* out, int64_t nreal, hipStream_t s);
 int assemble_t2_blocks(int64_t npairs);
 void k_reduce_sum(const double* partial, int n, int width, double* out, hipStream_t s);
 void k_dot_many(const double* const* es, int m, const double* e, int64_t len, double* partial,

@@ -13,16 +13,20 @@ constexpr int TB = 256;
 struct z {
   double x, y;
 };
-__device__ __forceinline__ z ld(const double* p, int64_t i) {
-  typedef double v2 __attribute__((ext_vector_type(2)));
+// complex element i of an interleaved array of T (float or double), widened to double
+template <typename T>
+__device__ __forceinline__ z ld(const T* p, int64_t i) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
   v2 t = *reinterpret_cast<const v2*>(p + 2 * i);
-  return z{t.x, t.y};
+  return z{(double)t.x, (double)t.y};
 }
-__device__ __forceinline__ void st(double* p, int64_t i, z v) {
-  typedef double v2 __attribute__((ext_vector_type(2)));
+// store complex element i, rounded to T (round to nearest even)
+template <typename T>
+__device__ __forceinline__ void st(T* p, int64_t i, z v) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
   v2 t;
-  t.x = v.x;
-  t.y = v.y;
+  t.x = (T)v.x;
+  t.y = (T)v.y;
   *reinterpret_cast<v2*>(p + 2 * i) = t;
 }
 __device__ __forceinline__ z add(z a, z b) { return z{a.x + b.x, a.y + b.y}; }
@@ -122,7 +126,8 @@ __global__ void check_B_final(const double* __restrict__ part, int nb, double* _
 }
 
 // ------------------------------------------------------------------ packing
-__global__ void pack_last2_kernel(double* __restrict__ out, const double* __restrict__ in,
+template <typename T>
+__global__ void pack_last2_kernel(T* __restrict__ out, const T* __restrict__ in,
                                   const int* __restrict__ rowmap, int64_t rows, int m,
                                   int64_t in_row_stride) {
   const int64_t P = (int64_t)m * (m - 1) / 2, tot = rows * P;
@@ -136,9 +141,10 @@ __global__ void pack_last2_kernel(double* __restrict__ out, const double* __rest
 }
 
 // T2 (full), TAU (full) and packed tau from t1 and packed t2.
+template <typename T>
 __global__ void unpack_tau_kernel(const double* __restrict__ t1, const double* __restrict__ t2p,
-                                  double* __restrict__ T2, double* __restrict__ TAU,
-                                  double* __restrict__ taup, int o, int v) {
+                                  T* __restrict__ T2, T* __restrict__ TAU, T* __restrict__ taup, int o,
+                                  int v) {
   const int64_t vv = (int64_t)v * v, tot = (int64_t)o * o * vv, Pv = (int64_t)v * (v - 1) / 2;
   for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
     const int64_t ij = t / vv, ab = t - ij * vv;
@@ -161,8 +167,9 @@ __global__ void unpack_tau_kernel(const double* __restrict__ t1, const double* _
 }
 
 // Tq[b][j][k][c] = T2[j][k][c][b];  Xp[b][j][k][c] = 1/2 Tq + t1[k][b] t1[j][c]
-__global__ void ring_operands_kernel(const double* __restrict__ T2, const double* __restrict__ t1,
-                                     double* __restrict__ Tq, double* __restrict__ Xp, int o, int v) {
+template <typename T>
+__global__ void ring_operands_kernel(const T* __restrict__ T2, const double* __restrict__ t1,
+                                     T* __restrict__ Tq, T* __restrict__ Xp, int o, int v) {
   __shared__ double tr[32][33], ti[32][33];
   const int b0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
   const int64_t jk = blockIdx.z;
@@ -190,8 +197,9 @@ __global__ void ring_operands_kernel(const double* __restrict__ T2, const double
 }
 
 // Cf[i][j][b][k] = conj(Vooov[i][j][k][b]) + sign(i,j) Cp[(min,max)][b][k]
-__global__ void expand_c_kernel(const double* __restrict__ Vooov, const double* __restrict__ Cp,
-                                double* __restrict__ Cf, int o, int v) {
+template <typename T>
+__global__ void expand_c_kernel(const T* __restrict__ Vooov, const T* __restrict__ Cp,
+                                T* __restrict__ Cf, int o, int v) {
   const int64_t tot = (int64_t)o * o * v * o;
   for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
     int64_t r = t;
@@ -213,8 +221,8 @@ __global__ void expand_c_kernel(const double* __restrict__ Vooov, const double* 
 }
 
 // W[b'][x=(c<d)] = Ta[c][b'][d] - Ta[d][b'][c]
-__global__ void ladder_antisym_kernel(const double* __restrict__ Ta, double* __restrict__ W, int nb,
-                                      int v) {
+template <typename T>
+__global__ void ladder_antisym_kernel(const T* __restrict__ Ta, T* __restrict__ W, int nb, int v) {
   const int64_t Pv = (int64_t)v * (v - 1) / 2, tot = (int64_t)nb * Pv;
   for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
     const int64_t bp = t / Pv, x = t - bp * Pv;
@@ -227,8 +235,9 @@ __global__ void ladder_antisym_kernel(const double* __restrict__ Ta, double* __r
 }
 
 // Residual assembly + Jacobi step for the doubles (packed i<j, a<b).
-__global__ void assemble_t2_kernel(const double* __restrict__ Znp, const double* __restrict__ Zab,
-                                   const double* __restrict__ Zij, const double* __restrict__ R,
+template <typename T>
+__global__ void assemble_t2_kernel(const T* __restrict__ Znp, const T* __restrict__ Zab,
+                                   const T* __restrict__ Zij, const T* __restrict__ R,
                                    const double* __restrict__ Vp, const double* __restrict__ t2p,
                                    const double* __restrict__ eps, int o, int v, double shift,
                                    double* __restrict__ xt, double* __restrict__ e,
@@ -277,7 +286,8 @@ __global__ void assemble_t2_kernel(const double* __restrict__ Znp, const double*
   if (threadIdx.x == 0 && part) part[blockIdx.x] = sh[0];
 }
 
-__global__ void assemble_t1_kernel(const double* __restrict__ S1, const double* __restrict__ t1,
+template <typename T>
+__global__ void assemble_t1_kernel(const T* __restrict__ S1, const double* __restrict__ t1,
                                    const double* __restrict__ eps, int o, int v, double shift,
                                    double* __restrict__ xt, double* __restrict__ e,
                                    double* __restrict__ s1, double* __restrict__ part) {
@@ -437,9 +447,19 @@ __global__ void pack_amp_kernel(const double* __restrict__ t2, double* __restric
   }
 }
 
+__global__ void cast_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB)
+    out[t] = (float)in[t];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+void k_cast(const double* in, float* out, int64_t nreal, hipStream_t s) {
+  if (nreal <= 0) return;
+  hipLaunchKernelGGL(cast_kernel, dim3(nblocks(nreal)), dim3(TB), 0, s, in, out, nreal);
+  HIPCHECK(hipGetLastError());
+}
 void k_transpose_B(const double* B, double* Bt, int64_t X, int64_t nn, hipStream_t s) {
   dim3 grid((unsigned)((nn + 31) / 32), (unsigned)((X + 31) / 32)), block(32, 8);
   hipLaunchKernelGGL(transpose_B_kernel, grid, block, 0, s, B, Bt, X, nn);
@@ -454,42 +474,46 @@ void k_check_B(const double* B, int64_t X, int n, double* out3, double* scratch,
   HIPCHECK(hipGetLastError());
 }
 
-void k_pack_last2(double* out, const double* in, const int* rowmap, int64_t rows, int m,
-                  int64_t in_row_stride, hipStream_t s) {
+template <typename T>
+void k_pack_last2(T* out, const T* in, const int* rowmap, int64_t rows, int m, int64_t in_row_stride,
+                  hipStream_t s) {
   const int64_t tot = rows * ((int64_t)m * (m - 1) / 2);
   if (tot <= 0) return;
-  hipLaunchKernelGGL(pack_last2_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, out, in, rowmap, rows, m,
-                     in_row_stride);
+  hipLaunchKernelGGL(pack_last2_kernel<T>, dim3(nblocks(tot)), dim3(TB), 0, s, out, in, rowmap, rows,
+                     m, in_row_stride);
   HIPCHECK(hipGetLastError());
 }
 
-void k_unpack_tau(const double* t1, const double* t2p, double* T2, double* TAU, double* taup, int o,
-                  int v, hipStream_t s) {
+template <typename T>
+void k_unpack_tau(const double* t1, const double* t2p, T* T2, T* TAU, T* taup, int o, int v,
+                  hipStream_t s) {
   const int64_t tot = (int64_t)o * o * v * v;
-  hipLaunchKernelGGL(unpack_tau_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, t1, t2p, T2, TAU, taup, o,
-                     v);
+  hipLaunchKernelGGL(unpack_tau_kernel<T>, dim3(nblocks(tot)), dim3(TB), 0, s, t1, t2p, T2, TAU, taup,
+                     o, v);
   HIPCHECK(hipGetLastError());
 }
 
-void k_ring_operands(const double* T2, const double* t1, double* Tq, double* Xp, int o, int v,
-                     hipStream_t s) {
+template <typename T>
+void k_ring_operands(const T* T2, const double* t1, T* Tq, T* Xp, int o, int v, hipStream_t s) {
   const int64_t oo = (int64_t)o * o;
   if (oo > 65535) raise(-5, "nocc too large for ring operand permute");
   dim3 grid((v + 31) / 32, (v + 31) / 32, (unsigned)oo), block(32, 8);
-  hipLaunchKernelGGL(ring_operands_kernel, grid, block, 0, s, T2, t1, Tq, Xp, o, v);
+  hipLaunchKernelGGL(ring_operands_kernel<T>, grid, block, 0, s, T2, t1, Tq, Xp, o, v);
   HIPCHECK(hipGetLastError());
 }
 
-void k_expand_c(const double* Vooov, const double* Cp, double* Cf, int o, int v, hipStream_t s) {
+template <typename T>
+void k_expand_c(const T* Vooov, const T* Cp, T* Cf, int o, int v, hipStream_t s) {
   const int64_t tot = (int64_t)o * o * o * v;
-  hipLaunchKernelGGL(expand_c_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, Vooov, Cp, Cf, o, v);
+  hipLaunchKernelGGL(expand_c_kernel<T>, dim3(nblocks(tot)), dim3(TB), 0, s, Vooov, Cp, Cf, o, v);
   HIPCHECK(hipGetLastError());
 }
 
-void k_ladder_antisym(const double* Ta, double* W, int nb, int v, hipStream_t s) {
+template <typename T>
+void k_ladder_antisym(const T* Ta, T* W, int nb, int v, hipStream_t s) {
   const int64_t tot = (int64_t)nb * ((int64_t)v * (v - 1) / 2);
   if (tot <= 0) return;
-  hipLaunchKernelGGL(ladder_antisym_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, Ta, W, nb, v);
+  hipLaunchKernelGGL(ladder_antisym_kernel<T>, dim3(nblocks(tot)), dim3(TB), 0, s, Ta, W, nb, v);
   HIPCHECK(hipGetLastError());
 }
 
@@ -497,18 +521,19 @@ int assemble_t2_blocks(int64_t npairs) { return nblocks(npairs, 4096); }
 int dot_many_blocks(int64_t len) { return nblocks(len, 2048); }
 int energy_blocks(int64_t npairs) { return nblocks(npairs, 2048); }
 
-void k_assemble_t2(const double* Znp, const double* Zab, const double* Zij, const double* R,
-                   const double* Voovv_p, const double* t2p, const double* eps, int o, int v,
-                   double shift, double* xt, double* e, double* s2_full, double* partial, int nblk,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(assemble_t2_kernel, dim3(nblk), dim3(TB), 0, s, Znp, Zab, Zij, R, Voovv_p, t2p,
+template <typename T>
+void k_assemble_t2(const T* Znp, const T* Zab, const T* Zij, const T* R, const double* Voovv_p,
+                   const double* t2p, const double* eps, int o, int v, double shift, double* xt,
+                   double* e, double* s2_full, double* partial, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(assemble_t2_kernel<T>, dim3(nblk), dim3(TB), 0, s, Znp, Zab, Zij, R, Voovv_p, t2p,
                      eps, o, v, shift, xt, e, s2_full, partial);
   HIPCHECK(hipGetLastError());
 }
 
-void k_assemble_t1(const double* S1, const double* t1, const double* eps, int o, int v, double shift,
+template <typename T>
+void k_assemble_t1(const T* S1, const double* t1, const double* eps, int o, int v, double shift,
                    double* xt, double* e, double* s1_full, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(assemble_t1_kernel, dim3(1), dim3(TB), 0, s, S1, t1, eps, o, v, shift, xt, e,
+  hipLaunchKernelGGL(assemble_t1_kernel<T>, dim3(1), dim3(TB), 0, s, S1, t1, eps, o, v, shift, xt, e,
                      s1_full, partial);
   HIPCHECK(hipGetLastError());
 }
@@ -562,5 +587,20 @@ void k_pack_amplitudes(const double* t1, const double* t2, double* x, int o, int
   hipLaunchKernelGGL(pack_amp_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, t2, x, o, v);
   HIPCHECK(hipGetLastError());
 }
+
+#define EXACC_INST(T)                                                                          \
+  template void k_pack_last2<T>(T*, const T*, const int*, int64_t, int, int64_t, hipStream_t);   \
+  template void k_unpack_tau<T>(const double*, const double*, T*, T*, T*, int, int, hipStream_t); \
+  template void k_ring_operands<T>(const T*, const double*, T*, T*, int, int, hipStream_t);      \
+  template void k_expand_c<T>(const T*, const T*, T*, int, int, hipStream_t);                    \
+  template void k_ladder_antisym<T>(const T*, T*, int, int, hipStream_t);                        \
+  template void k_assemble_t2<T>(const T*, const T*, const T*, const T*, const double*,          \
+                                 const double*, const double*, int, int, double, double*,        \
+                                 double*, double*, double*, int, hipStream_t);                   \
+  template void k_assemble_t1<T>(const T*, const double*, const double*, int, int, double,       \
+                                 double*, double*, double*, double*, hipStream_t);
+EXACC_INST(double)
+EXACC_INST(float)
+#undef EXACC_INST
 
 }  // namespace exacc

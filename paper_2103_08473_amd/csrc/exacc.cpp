@@ -102,6 +102,8 @@ static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
   add("Ta", (int64_t)v * std::max(1, v - 1) * v);
   add("W", p.chunk_pairs * std::max<int64_t>(1, p.Pv));
   add("splitk_ws", (256ll << 20) / 16);
+  if (op.precision == EXACC_MIXED_FP32)  // FP32 copies of B and the stored classes
+    add("fp32_copies", (n * n * X + oo * oo + oo * o * v + 2 * p.oovv + (int64_t)v * o * p.Pv + 1) / 2);
   add("Braw", n * n * X, true);
   add("vovv_tmp", p.vovv_chunk * vovv_row, true);
   size_t pers = 0, tr = 0;
@@ -154,7 +156,13 @@ struct Handle {
   double *Bt = nullptr, *Voooo, *Vooov, *Voovv, *Voovv_p, *Vvovo, *Vvovv_p;
   double *x, *diis, *T2, *TAU, *taup, *Tq, *Xp, *H4, *R, *Zij, *Zab, *Znp;
   double *Hac, *Gac, *Hki, *Gki, *Hkc, *y, *Zt, *U, *Vt, *M1, *Y, *S1, *Cp, *Cf, *Af, *Ap;
-  double *Ta, *W;
+  double *Ta, *W, *t1w;
+  // FP32 copies of B and the stored integral classes (mixed precision only)
+  float *Bt32 = nullptr, *Voooo32 = nullptr, *Vooov32 = nullptr, *Voovv32 = nullptr,
+        *Vvovo32 = nullptr, *Vvovv_p32 = nullptr;
+  bool phase32 = false;       // current iteration runs its contractions in FP32
+  bool last32 = false;        // the last completed iteration ran in FP32
+  int fp64_iters = 0;         // FP64 iterations since the last switch
   double* red = nullptr;      // reduction partials
   double* redout = nullptr;   // reduced values (device)
   double* host = nullptr;     // pinned readback
@@ -226,30 +234,63 @@ static void timer_collect(Handle& h) {
 static const cplx ONE{1, 0}, MONE{-1, 0}, HALF{0.5, 0};
 
 // ------------------------------------------------------------------ views
-struct Views {
-  TV<double> Bvv, Bov, Bvo, Boo;
+// Typed pointers for one precision.  R = double: the FP64 buffers.  R = float:
+// FP32 integral copies; the work arrays alias the FP64 buffers (half their size).
+template <typename R>
+struct Work {
+  R *Bt, *Voooo, *Vooov, *Voovv, *Vvovo, *Vvovv_p;
+  R *T2, *TAU, *taup, *Tq, *Xp, *H4, *R_, *Zij, *Zab, *Znp;
+  R *Hac, *Gac, *Hki, *Gki, *Hkc, *y, *Zt, *U, *Vt, *M1, *Y, *S1, *Cp, *Cf, *Af, *Ap, *Ta, *W;
+  R* t1;  // t1 in R, as a contraction operand
 };
-static Views bviews(Handle& h) {
+template <typename R>
+static Work<R> work(Handle& h);
+template <>
+Work<double> work<double>(Handle& h) {
+  return Work<double>{h.Bt, h.Voooo, h.Vooov, h.Voovv, h.Vvovo, h.Vvovv_p, h.T2, h.TAU, h.taup,
+                      h.Tq, h.Xp, h.H4, h.R, h.Zij, h.Zab, h.Znp, h.Hac, h.Gac, h.Hki, h.Gki,
+                      h.Hkc, h.y, h.Zt, h.U, h.Vt, h.M1, h.Y, h.S1, h.Cp, h.Cf, h.Af, h.Ap, h.Ta, h.W,
+                      h.t1w};
+}
+template <>
+Work<float> work<float>(Handle& h) {
+  auto f = [](double* p) { return reinterpret_cast<float*>(p); };
+  return Work<float>{h.Bt32, h.Voooo32, h.Vooov32, h.Voovv32, h.Vvovo32, h.Vvovv_p32,
+                     f(h.T2), f(h.TAU), f(h.taup), f(h.Tq), f(h.Xp), f(h.H4), f(h.R), f(h.Zij),
+                     f(h.Zab), f(h.Znp), f(h.Hac), f(h.Gac), f(h.Hki), f(h.Gki), f(h.Hkc),
+                     f(h.y), f(h.Zt), f(h.U), f(h.Vt), f(h.M1), f(h.Y), f(h.S1), f(h.Cp),
+                     f(h.Cf), f(h.Af), f(h.Ap), f(h.Ta), f(h.W), f(h.t1w)};
+}
+
+template <typename R>
+struct Views {
+  TV<R> Bvv, Bov, Bvo, Boo;
+};
+template <typename R>
+static Views<R> bviews(Handle& h, R* Bt) {
   const int o = h.P.o, v = h.P.v, X = h.P.X, n = h.P.n;
-  Views w;
+  Views<R> w;
   const int64_t nX = (int64_t)n * X;
-  w.Boo = sview(h.Bt, {o, o, X}, {nX, X, 1});
-  w.Bov = sview(h.Bt + 2 * (int64_t)o * X, {o, v, X}, {nX, X, 1});
-  w.Bvo = sview(h.Bt + 2 * (int64_t)o * nX, {v, o, X}, {nX, X, 1});
-  w.Bvv = sview(h.Bt + 2 * ((int64_t)o * nX + (int64_t)o * X), {v, v, X}, {nX, X, 1});
+  w.Boo = sview(Bt, {o, o, X}, {nX, X, 1});
+  w.Bov = sview(Bt + 2 * (int64_t)o * X, {o, v, X}, {nX, X, 1});
+  w.Bvo = sview(Bt + 2 * (int64_t)o * nX, {v, o, X}, {nX, X, 1});
+  w.Bvv = sview(Bt + 2 * ((int64_t)o * nX + (int64_t)o * X), {v, v, X}, {nX, X, 1});
   return w;
 }
 
-static void dcopy(Handle& h, double* dst, const double* src, int64_t celems) {
-  if (celems > 0) HIPCHECK(hipMemcpyAsync(dst, src, celems * 16, hipMemcpyDeviceToDevice, h.s));
+template <typename R>
+static void dcopy(Handle& h, R* dst, const R* src, int64_t celems) {
+  if (celems > 0)
+    HIPCHECK(hipMemcpyAsync(dst, src, celems * 2 * sizeof(R), hipMemcpyDeviceToDevice, h.s));
 }
+
 
 // ------------------------------------------------------------------ integrals (create)
 static void build_integrals(Handle& h, double* vovv_tmp) {
   Scope sc(h, "integrals");
   const int o = h.P.o, v = h.P.v;
   const hipStream_t s = h.s;
-  Views b = bviews(h);
+  Views<double> b = bviews(h, h.Bt);
   // <kl||ij> = (ki|lj) - (kj|li)
   auto Voooo = view(h.Voooo, {o, o, o, o});
   contract(s, "kiP,ljP->klij", ONE, b.Boo, b.Boo, false, Voooo);
@@ -287,65 +328,71 @@ static void build_integrals(Handle& h, double* vovv_tmp) {
 // Fills S1 (singles, without the diagonal Fock part) and the doubles pieces
 // Znp (no permutation), Zab (P_ab), Zij (P_ij), R (P_ij P_ab) for the
 // amplitudes in h.x.
+template <typename R>
 static void compute_residual(Handle& h) {
+  Work<R> w = work<R>(h);
   const int o = h.P.o, v = h.P.v, X = h.P.X;
   const int64_t Po = h.P.Po, Pv = h.P.Pv;
   const hipStream_t s = h.s;
-  Views b = bviews(h);
+  Views<R> b = bviews(h, w.Bt);
   const double* t1p = h.x;
   const double* t2p = h.x + 2 * (int64_t)o * v;
-  auto t1 = view((double*)t1p, {o, v});
-  auto T2 = view(h.T2, {o, o, v, v});
-  auto TAU = view(h.TAU, {o, o, v, v});
-  auto taup = view(h.taup, {Po, Pv});
-  auto Voovv = view(h.Voovv, {o, o, v, v});
-  auto Vooov = view(h.Vooov, {o, o, o, v});
-  auto Vvovo = view(h.Vvovo, {v, o, o, v});
+  auto t1 = view(w.t1, {o, v});
+  auto T2 = view(w.T2, {o, o, v, v});
+  auto TAU = view(w.TAU, {o, o, v, v});
+  auto taup = view(w.taup, {Po, Pv});
+  auto Voovv = view(w.Voovv, {o, o, v, v});
+  auto Vooov = view(w.Vooov, {o, o, o, v});
+  auto Vvovo = view(w.Vvovo, {v, o, o, v});
   {
     Scope sc(h, "prep");
-    k_unpack_tau(t1p, t2p, h.T2, h.TAU, h.taup, o, v, s);
-    k_ring_operands(h.T2, t1p, h.Tq, h.Xp, o, v, s);
+    if (sizeof(R) == sizeof(double))
+      dcopy(h, (double*)w.t1, h.x, (int64_t)o * v);
+    else
+      k_cast(h.x, (float*)w.t1, 2 * (int64_t)o * v, s);
+    k_unpack_tau<R>(t1p, t2p, w.T2, w.TAU, w.taup, o, v, s);
+    k_ring_operands<R>(w.T2, t1p, w.Tq, w.Xp, o, v, s);
   }
-  auto Hac = view(h.Hac, {v, v}), Gac = view(h.Gac, {v, v});
-  auto Hki = view(h.Hki, {o, o}), Gki = view(h.Gki, {o, o});
-  auto Hkc = view(h.Hkc, {o, v});
+  auto Hac = view(w.Hac, {v, v}), Gac = view(w.Gac, {v, v});
+  auto Hki = view(w.Hki, {o, o}), Gki = view(w.Gki, {o, o});
+  auto Hkc = view(w.Hkc, {o, v});
   {
     Scope sc(h, "onebody");
     contract(s, "klcd,klda->ac", HALF, Voovv, TAU, false, Hac);
     contract(s, "klcd,licd->ki", HALF, Voovv, TAU, false, Hki);
     contract(s, "klcd,ld->kc", ONE, Voovv, t1, false, Hkc);
-    dcopy(h, h.Gac, h.Hac, (int64_t)v * v);
-    dcopy(h, h.Gki, h.Hki, (int64_t)o * o);
+    dcopy(h, w.Gac, w.Hac, (int64_t)v * v);
+    dcopy(h, w.Gki, w.Hki, (int64_t)o * o);
     // sum_kd <ak||cd> t_k^d = sum_P B_ac^P (sum_kd B_kd^P t_k^d) - sum_Pd B_ad^P (sum_k t_k^d B_kc^P)
-    auto y = view(h.y, {X});
+    auto y = view(w.y, {X});
     contract(s, "kdP,kd->P", ONE, b.Bov, t1, false, y);
     contract(s, "acP,P->ac", ONE, b.Bvv, y, true, Gac);
-    auto Zt = view(h.Zt, {v, v, X});
+    auto Zt = view(w.Zt, {v, v, X});
     contract(s, "kd,kcP->dcP", ONE, t1, b.Bov, false, Zt);
     contract(s, "adP,dcP->ac", MONE, b.Bvv, Zt, true, Gac);
     contract(s, "klic,lc->ki", MONE, Vooov, t1, true, Gki);
   }
-  auto H4 = view(h.H4, {v, o, o, v});
-  auto U = view(h.U, {o, o, X});
-  auto Vt = view(h.Vt, {v, o, X});
+  auto H4 = view(w.H4, {v, o, o, v});
+  auto U = view(w.U, {o, o, X});
+  auto Vt = view(w.Vt, {v, o, X});
   {
     Scope sc(h, "ring_build");
-    dcopy(h, h.H4, h.Vvovo, h.P.oovv);
+    dcopy(h, w.H4, w.Vvovo, h.P.oovv);
     contract(s, "kdP,id->kiP", ONE, b.Bov, t1, false, U);
     contract(s, "acP,ic->aiP", ONE, b.Bvv, t1, false, Vt);
     contract(s, "acP,kiP->aikc", ONE, b.Bvv, U, true, H4);
     contract(s, "aiP,kcP->aikc", MONE, Vt, b.Bov, true, H4);
     contract(s, "klic,la->aikc", MONE, Vooov, t1, true, H4);
-    contract(s, "aild,klcd->aikc", ONE, view(h.Xp, {v, o, o, v}), Voovv, true, H4, GETT_RING);
+    contract(s, "aild,klcd->aikc", ONE, view(w.Xp, {v, o, o, v}), Voovv, true, H4, GETT_RING);
   }
-  auto R = view(h.R, {o, o, v, v});
+  auto Rv = view(w.R_, {o, o, v, v});
   {
     Scope sc(h, "ring");
-    contract(s, "aikc,bjkc->ijab", ONE, H4, view(h.Tq, {v, o, o, v}), false, R, GETT_RING);
-    contract(s, "aiP,bjP->ijab", ONE, Vt, b.Bvo, true, R);
+    contract(s, "aikc,bjkc->ijab", ONE, H4, view(w.Tq, {v, o, o, v}), false, Rv, GETT_RING);
+    contract(s, "aiP,bjP->ijab", ONE, Vt, b.Bvo, true, Rv);
   }
-  auto Zij = view(h.Zij, {o, o, v, v});
-  auto Zab = view(h.Zab, {o, o, v, v});
+  auto Zij = view(w.Zij, {o, o, v, v});
+  auto Zab = view(w.Zab, {o, o, v, v});
   {
     Scope sc(h, "fock_terms");
     contract(s, "kj,ikab->ijab", ONE, Gki, T2, false, Zij);
@@ -353,24 +400,24 @@ static void compute_residual(Handle& h) {
   }
   {
     Scope sc(h, "cterm");
-    auto Cp = view(h.Cp, {Po, v, o});
-    contract(s, "bkx,px->pbk", MONE, view(h.Vvovv_p, {v, o, Pv}), taup, false, Cp);
-    k_expand_c(h.Vooov, h.Cp, h.Cf, o, v, s);
-    auto Cf = view(h.Cf, {o, o, v, o});
+    auto Cp = view(w.Cp, {Po, v, o});
+    contract(s, "bkx,px->pbk", MONE, view(w.Vvovv_p, {v, o, Pv}), taup, false, Cp);
+    k_expand_c<R>(w.Vooov, w.Cp, w.Cf, o, v, s);
+    auto Cf = view(w.Cf, {o, o, v, o});
     contract(s, "bikc,jc->ijbk", ONE, Vvovo, t1, true, Cf);
     contract(s, "bjkc,ic->ijbk", MONE, Vvovo, t1, true, Cf);
     contract(s, "ijak,kb->ijab", ONE, Cf, t1, true, Zab);
   }
-  auto Znp = view(h.Znp, {Po, Pv});
+  auto Znp = view(w.Znp, {Po, Pv});
   {
     Scope sc(h, "hole_ladder");
-    auto Af = view(h.Af, {o, o, o, o});
-    dcopy(h, h.Af, h.Voooo, (int64_t)o * o * o * o);
+    auto Af = view(w.Af, {o, o, o, o});
+    dcopy(h, w.Af, w.Voooo, (int64_t)o * o * o * o);
     contract(s, "klic,jc->klij", ONE, Vooov, t1, true, Af);
     contract(s, "kljc,ic->klij", MONE, Vooov, t1, true, Af);
     contract(s, "klcd,ijcd->klij", HALF, Voovv, TAU, true, Af);
-    if (Po > 0) k_pack_last2(h.Ap, h.Af, h.rowmap_o, Po, o, (int64_t)o * o, s);
-    contract(s, "qp,qx->px", ONE, view(h.Ap, {Po, Po}), taup, false, Znp);
+    if (Po > 0) k_pack_last2<R>(w.Ap, w.Af, h.rowmap_o, Po, o, (int64_t)o * o, s);
+    contract(s, "qp,qx->px", ONE, view(w.Ap, {Po, Po}), taup, false, Znp);
   }
   // particle ladder: Znp[ij][ab] += sum_{c<d} tau[ij][cd] <ab||cd>, <ab||cd> = (ac|bd) - (ad|bc)
   if (Po > 0 && Pv > 0) {
@@ -379,8 +426,8 @@ static void compute_residual(Handle& h) {
     auto flush = [&]() {
       if (rows == 0) return;
       Scope sc(h, "ladder_contract");
-      auto Wv = view(h.W, {rows, Pv});
-      auto Zc = sview(h.Znp + 2 * start, {Po, rows}, {Pv, 1});
+      auto Wv = view(w.W, {rows, Pv});
+      auto Zc = sview(w.Znp + 2 * start, {Po, rows}, {Pv, 1});
       contract(s, "py,xy->px", ONE, taup, Wv, true, Zc, GETT_LADDER_CONTRACT);
       start += rows;
       rows = 0;
@@ -392,11 +439,11 @@ static void compute_residual(Handle& h) {
         Scope sc(h, "ladder_build");
         auto Ba = sview(b.Bvv.p + 2 * (int64_t)a * nX, {v, X}, {X, 1});
         auto Bb = sview(b.Bvv.p + 2 * (int64_t)(a + 1) * nX, {nb, v, X}, {nX, X, 1});
-        contract(s, "cP,bdP->cbd", ONE, Ba, Bb, false, view(h.Ta, {v, nb, v}), GETT_LADDER_BUILD);
+        contract(s, "cP,bdP->cbd", ONE, Ba, Bb, false, view(w.Ta, {v, nb, v}), GETT_LADDER_BUILD);
       }
       {
         Scope sc(h, "ladder_antisym");
-        k_ladder_antisym(h.Ta, h.W + 2 * rows * Pv, nb, v, s);
+        k_ladder_antisym<R>(w.Ta, w.W + 2 * rows * Pv, nb, v, s);
       }
       rows += nb;
     }
@@ -404,14 +451,14 @@ static void compute_residual(Handle& h) {
   }
   {
     Scope sc(h, "singles");
-    auto S1 = view(h.S1, {o, v});
+    auto S1 = view(w.S1, {o, v});
     contract(s, "ac,ic->ia", ONE, Hac, t1, false, S1);
     contract(s, "ki,ka->ia", ONE, Hki, t1, true, S1);
     contract(s, "kc,ikac->ia", ONE, Hkc, T2, true, S1);
-    auto M1 = view(h.M1, {o, o});
+    auto M1 = view(w.M1, {o, o});
     contract(s, "kc,ic->ki", ONE, Hkc, t1, false, M1);
     contract(s, "ki,ka->ia", ONE, M1, t1, true, S1);
-    auto Y = view(h.Y, {o, v, X});
+    auto Y = view(w.Y, {o, v, X});
     contract(s, "ikcd,kdP->icP", ONE, TAU, b.Bov, false, Y);
     contract(s, "icP,acP->ia", ONE, Y, b.Bvv, true, S1);
     contract(s, "klic,klca->ia", HALF, Vooov, TAU, true, S1);
@@ -502,6 +549,33 @@ static std::vector<zc> diis_solve(const std::vector<std::vector<zc>>& Gm) {
   return r;
 }
 
+// ------------------------------------------------------------------ assembly
+// Sum the residual pieces (precision R) with the FP64 driver and diagonal Fock
+// part; either take the Jacobi step into (xt, e) with |step|^2 partials, or
+// write the full residual into (s1, s2).
+template <typename R>
+static int assemble(Handle& h, double* xt, double* e, double* s1, double* s2, double shift) {
+  Work<R> w = work<R>(h);
+  const int o = h.P.o, v = h.P.v;
+  const int64_t ov = (int64_t)o * v, np = h.P.Po * h.P.Pv;
+  k_assemble_t1<R>(w.S1, h.x, h.eps, o, v, shift, xt, e, s1, s1 ? nullptr : h.red, h.s);
+  int nb = 0;
+  if (np > 0) {
+    nb = assemble_t2_blocks(np);
+    k_assemble_t2<R>(w.Znp, w.Zab, w.Zij, w.R_, h.Voovv_p, h.x + 2 * ov, h.eps, o, v, shift,
+                     xt ? xt + 2 * ov : nullptr, e ? e + 2 * ov : nullptr, s2,
+                     s2 ? nullptr : h.red + 1, nb, h.s);
+  }
+  return nb;
+}
+
+static void compute_residual_phase(Handle& h) {
+  if (h.phase32)
+    compute_residual<float>(h);
+  else
+    compute_residual<double>(h);
+}
+
 // ------------------------------------------------------------------ one iteration
 static zc device_energy(Handle& h) {
   Scope sc(h, "energy");
@@ -519,7 +593,8 @@ static zc device_energy(Handle& h) {
 static double one_iteration(Handle& h) {
   const int o = h.P.o, v = h.P.v;
   const int64_t ov = (int64_t)o * v, L = h.P.L;
-  compute_residual(h);
+  const bool was32 = h.phase32;
+  compute_residual_phase(h);
   // pick the DIIS slot (drop the oldest pair when full)
   const int cap = h.P.nslots;
   if ((int)h.order.size() == cap) {
@@ -532,14 +607,8 @@ static double one_iteration(Handle& h) {
   double* e = h.slot_e(slot);
   {
     Scope sc(h, "assemble");
-    k_assemble_t1(h.S1, h.x, h.eps, o, v, h.op.level_shift, xt, e, nullptr, h.red, h.s);
-    const int64_t np = h.P.Po * h.P.Pv;
-    int nb = 0;
-    if (np > 0) {
-      nb = assemble_t2_blocks(np);
-      k_assemble_t2(h.Znp, h.Zab, h.Zij, h.R, h.Voovv_p, h.x + 2 * ov, h.eps, o, v, h.op.level_shift,
-                    xt + 2 * ov, e + 2 * ov, nullptr, h.red + 1, nb, h.s);
-    }
+    const int nb = was32 ? assemble<float>(h, xt, e, nullptr, nullptr, h.op.level_shift)
+                         : assemble<double>(h, xt, e, nullptr, nullptr, h.op.level_shift);
     k_reduce_sum(h.red, nb + 1, 1, h.redout, h.s);
   }
   // Gram row of the new error vector against every stored one (and itself)
@@ -594,6 +663,15 @@ static double one_iteration(Handle& h) {
   h.energy = device_energy(h);
   timer_collect(h);
   h.iters++;
+  // precision schedule: FP32 contractions until the step norm falls below the
+  // switch threshold, then FP64 contractions with a fresh DIIS subspace
+  h.last32 = was32;
+  if (!was32) h.fp64_iters++;
+  if (was32 && rnorm < h.op.mixed_switch_tol) {
+    h.phase32 = false;
+    h.fp64_iters = 0;
+    h.order.clear();
+  }
   return rnorm;
 }
 
@@ -618,7 +696,8 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
   if (o < 1 || v < 1 || X < 1) raise(EXACC_ERR_INVALID_ARG, "nocc, nvir and naux must be >= 1");
   if (!eps || !B) raise(EXACC_ERR_INVALID_ARG, "null input pointer");
   if ((int64_t)o * o > 65535) raise(EXACC_ERR_INVALID_ARG, "nocc too large (nocc^2 > 65535)");
-  if (op.precision != EXACC_FP64) raise(EXACC_ERR_UNSUPPORTED, "only EXACC_FP64 is built");
+  if (op.precision != EXACC_FP64 && op.precision != EXACC_MIXED_FP32)
+    raise(EXACC_ERR_UNSUPPORTED, "precision mode not built (EXACC_FP64, EXACC_MIXED_FP32 are)");
   if (op.diis_size < 0 || op.diis_size > 16) raise(EXACC_ERR_INVALID_ARG, "diis_size must be 0..16");
   if (!(op.tol >= 0) || !std::isfinite(op.level_shift))
     raise(EXACC_ERR_INVALID_ARG, "bad tol or level_shift");
@@ -705,6 +784,7 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
     h->M1 = h->dalloc(oo);
     h->Hkc = h->dalloc((int64_t)o * v);
     h->S1 = h->dalloc((int64_t)o * v);
+    h->t1w = h->dalloc((int64_t)o * v);
     h->y = h->dalloc(X);
     h->Zt = h->dalloc(P.vv * X);
     h->U = h->dalloc(oo * X);
@@ -737,6 +817,22 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
       build_integrals(*h, tmp);
       HIPCHECK(hipStreamSynchronize(h->s));
       h->ranges.pop_back();
+      h->use();
+    }
+    if (op.precision == EXACC_MIXED_FP32) {
+      // FP32 copies of the factors and stored classes for the FP32 phase
+      auto mk32 = [&](const double* src64, int64_t celems) {
+        float* p = reinterpret_cast<float*>(h->dalloc((celems + 1) / 2));
+        k_cast(src64, p, 2 * celems, h->s);
+        return p;
+      };
+      h->Bt32 = mk32(h->Bt, nnX);
+      h->Voooo32 = mk32(h->Voooo, oo * oo);
+      h->Vooov32 = mk32(h->Vooov, oo * o * v);
+      h->Voovv32 = mk32(h->Voovv, P.oovv);
+      h->Vvovo32 = mk32(h->Vvovo, P.oovv);
+      h->Vvovv_p32 = mk32(h->Vvovv_p, (int64_t)v * o * P.Pv);
+      h->phase32 = true;
       h->use();
     }
     HIPCHECK(hipMemsetAsync(h->x, 0, P.L * 16, h->s));
@@ -824,7 +920,8 @@ int exacc_ccsd_iterate(exacc_ccsd_t hh, int max_steps, int* steps_done, double* 
       if (!std::isfinite(r) || !std::isfinite(h.energy.real()) || !std::isfinite(h.energy.imag()) ||
           r > 1e6 * std::max(h.first_norm, 1e-300))
         return (int)EXACC_ERR_DIVERGED;
-      if (r <= h.op.tol) {
+      const int need = h.op.precision == EXACC_FP64 ? 0 : h.op.fp64_final_iters;
+      if (r <= h.op.tol && !h.last32 && h.fp64_iters >= need) {
         if (converged) *converged = 1;
         return (int)EXACC_OK;
       }
@@ -892,21 +989,17 @@ int exacc_ccsd_residual(exacc_ccsd_t hh, double* s1, double* s2, int on_device) 
     Handle& h = *reinterpret_cast<Handle*>(hh);
     h.use();
     const int o = h.P.o, v = h.P.v;
-    compute_residual(h);
+    compute_residual_phase(h);
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    // reuse Tq as the full S2 buffer and Hkc as S1 output (both are rebuilt each iteration)
-    if (s1) {
-      k_assemble_t1(h.S1, h.x, h.eps, o, v, 0.0, nullptr, nullptr, h.Hkc, nullptr, h.s);
-      HIPCHECK(hipMemcpyAsync(s1, h.Hkc, (size_t)o * v * 16, k, h.s));
-    }
-    if (s2) {
-      HIPCHECK(hipMemsetAsync(h.Tq, 0, (size_t)h.P.oovv * 16, h.s));
-      const int64_t np = h.P.Po * h.P.Pv;
-      if (np > 0)
-        k_assemble_t2(h.Znp, h.Zab, h.Zij, h.R, h.Voovv_p, h.x + 2 * (int64_t)o * v, h.eps, o, v, 0.0,
-                      nullptr, nullptr, h.Tq, nullptr, assemble_t2_blocks(np), h.s);
-      HIPCHECK(hipMemcpyAsync(s2, h.Tq, (size_t)h.P.oovv * 16, k, h.s));
-    }
+    // full residual into Tq (FP64 buffer; its contents are rebuilt each iteration) and S1
+    // into the t1w buffer, both unused by the assembly
+    HIPCHECK(hipMemsetAsync(h.Tq, 0, (size_t)h.P.oovv * 16, h.s));
+    if (h.phase32)
+      assemble<float>(h, nullptr, nullptr, h.t1w, h.Tq, 0.0);
+    else
+      assemble<double>(h, nullptr, nullptr, h.t1w, h.Tq, 0.0);
+    if (s1) HIPCHECK(hipMemcpyAsync(s1, h.t1w, (size_t)o * v * 16, k, h.s));
+    if (s2) HIPCHECK(hipMemcpyAsync(s2, h.Tq, (size_t)h.P.oovv * 16, k, h.s));
     HIPCHECK(hipStreamSynchronize(h.s));
     timer_collect(h);
     return (int)EXACC_OK;
@@ -926,6 +1019,16 @@ int exacc_ccsd_stage_times(exacc_ccsd_t hh, const char** names, double* ms, int*
     *count = nn;
     if (reset)
       for (auto& x : h.tm.ms) x = 0.0;
+    return (int)EXACC_OK;
+  });
+}
+
+int exacc_ccsd_phase(exacc_ccsd_t hh, int* fp32, int* fp64_iters) {
+  return guarded([&] {
+    if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    if (fp32) *fp32 = h.phase32 ? 1 : 0;
+    if (fp64_iters) *fp64_iters = h.fp64_iters;
     return (int)EXACC_OK;
   });
 }

@@ -1,12 +1,15 @@
 // Complex GEMM-like tensor contraction (GETT) on CDNA4 matrix cores.
 //
-// One workgroup (4 waves of 64 lanes) owns a BM x BN tile of C.  Operand
-// tiles of BK = 16 complex columns are staged through LDS as separate real
-// and imaginary planes, k-major, so each 16x16x4 MFMA fragment is read with
-// unit stride.  A complex multiply-add is four real MFMAs (re*re, -im*im,
-// re*im, im*re) into two accumulators.  Global loads for the next k-tile are
-// issued into registers before the MFMAs of the current one (single LDS
-// buffer, register prefetch).  Operand addresses come from the composite
+// One workgroup (4 waves of 64 lanes) owns a BM x BN tile of C; two
+// workgroups per CU (two waves per SIMD) hide LDS and barrier latency.
+// Operand tiles of BK = 16 complex columns are staged through LDS as three
+// real planes, k-major: re, im and re+im, so each 16x16x4 MFMA fragment is
+// read with unit stride.  Complex products use the three-multiplication
+// (Gauss) form: T1 = re*re, T2 = im*im, T3 = (re+im)(re+im) accumulate in
+// three MFMA accumulators and C = (T1 - T2) + i (T3 - T1 - T2) at the end,
+// 3 real MFMAs per complex multiply-add instead of 4.  Global loads for the
+// next k-tile are issued into registers before the MFMAs of the current one
+// (single LDS buffer, register prefetch).  Operand addresses come from the composite
 // (outer, inner) index maps of Gett<R>, so permuted and strided tensors are
 // contracted in place without transposes in HBM.
 #include "common.h"
@@ -57,7 +60,7 @@ __device__ __forceinline__ C2<R> ldc(const R* p, int64_t off) {
 }
 
 template <typename R, int BM, int BN, bool AKF, bool BKF, int KIND>
-__global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
+__global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
   constexpr int BK = 16;
   constexpr int LA = BM + 1;  // odd row pitch: conflict-free k-major stores
   constexpr int LB = BN + 1;
@@ -67,8 +70,8 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
   constexpr int TN = BN / 32;
   typedef typename MF<R>::acc_t acc_t;
 
-  __shared__ R sA[2][BK][LA];
-  __shared__ R sB[2][BK][LB];
+  __shared__ R sA[3][BK][LA];  // re, im, re + im
+  __shared__ R sB[3][BK][LB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -191,6 +194,7 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
         const int m = tid / BK + 16 * q;
         sA[0][a_kk][m] = ra[q].x;
         sA[1][a_kk][m] = sa * ra[q].y;
+        sA[2][a_kk][m] = ra[q].x + sa * ra[q].y;
       }
     } else {
       constexpr int KS = 256 / BM;
@@ -199,6 +203,7 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
         const int k = a_kq + KS * q;
         sA[0][k][a_mm] = ra[q].x;
         sA[1][k][a_mm] = sa * ra[q].y;
+        sA[2][k][a_mm] = ra[q].x + sa * ra[q].y;
       }
     }
     if (BKF) {
@@ -207,6 +212,7 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
         const int n = tid / BK + 16 * q;
         sB[0][b_kk][n] = rb[q].x;
         sB[1][b_kk][n] = sb * rb[q].y;
+        sB[2][b_kk][n] = rb[q].x + sb * rb[q].y;
       }
     } else {
       constexpr int KS = 256 / BN;
@@ -215,17 +221,20 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
         const int k = b_kq + KS * q;
         sB[0][k][b_nn] = rb[q].x;
         sB[1][k][b_nn] = sb * rb[q].y;
+        sB[2][k][b_nn] = rb[q].x + sb * rb[q].y;
       }
     }
   };
 
-  acc_t accR[TM][TN], accI[TM][TN];
+  // accR, accI, accS hold T1 = sum re*re, T2 = sum im*im, T3 = sum (re+im)(re+im)
+  acc_t accR[TM][TN], accI[TM][TN], accS[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       accR[i][j] = acc_t{0, 0, 0, 0};
       accI[i][j] = acc_t{0, 0, 0, 0};
+      accS[i][j] = acc_t{0, 0, 0, 0};
     }
 
   const int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
@@ -239,27 +248,28 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
       const int kr = 4 * s + (lane >> 4);
-      R ar[TM], ai[TM], br[TN], bi[TN];
+      R ar[TM], ai[TM], as[TM], br[TN], bi[TN], bs[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int m = wm * (BM / 2) + 16 * i + (lane & 15);
         ar[i] = sA[0][kr][m];
         ai[i] = sA[1][kr][m];
+        as[i] = sA[2][kr][m];
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int n = wn * (BN / 2) + 16 * j + (lane & 15);
         br[j] = sB[0][kr][n];
         bi[j] = sB[1][kr][n];
+        bs[j] = sB[2][kr][n];
       }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
           accR[i][j] = MF<R>::mma(ar[i], br[j], accR[i][j]);
-          accR[i][j] = MF<R>::mma(-ai[i], bi[j], accR[i][j]);
-          accI[i][j] = MF<R>::mma(ar[i], bi[j], accI[i][j]);
-          accI[i][j] = MF<R>::mma(ai[i], br[j], accI[i][j]);
+          accI[i][j] = MF<R>::mma(ai[i], bi[j], accI[i][j]);
+          accS[i][j] = MF<R>::mma(as[i], bs[j], accS[i][j]);
         }
     }
     __syncthreads();
@@ -268,6 +278,16 @@ __global__ __launch_bounds__(256) void gett_kernel(Gett<R> g) {
       __syncthreads();
     }
   }
+
+  // complex result: re = T1 - T2, im = T3 - T1 - T2
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const acc_t t1 = accR[i][j], t2 = accI[i][j];
+      accR[i][j] = t1 - t2;
+      accI[i][j] = accS[i][j] - t1 - t2;
+    }
 
   // ---- epilogue (output layout of the 16x16 block per MF<R>::row)
   R* __restrict__ Cb = g.C + 2 * batch * g.c_b;

@@ -64,6 +64,8 @@ def load():
     L.exacc_ccsd_set_amplitudes.argtypes = [P, P, P, I]
     L.exacc_ccsd_residual.argtypes = [P, P, P, I]
     L.exacc_ccsd_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p), dp, ip, I]
+    L.exacc_ccsd_phase.argtypes = [P, ip, ip]
+    L.exacc_ccsd_phase.restype = I
     L.exacc_ladder_flops.argtypes = [I, I, I]
     L.exacc_ladder_flops.restype = D
     L.exacc_ccsd_destroy.argtypes = [P]
@@ -215,6 +217,12 @@ class CCSD:
         r2 = np.zeros((o, o, v, v), np.complex128)
         _check(self.L.exacc_ccsd_residual(self.h, r1.ctypes.data, r2.ctypes.data, 0))
         return r1, r2
+
+    def phase(self):
+        """(next step runs FP32 contractions, FP64 iterations since the switch)."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(self.L.exacc_ccsd_phase(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return bool(a.value), b.value
 
     def stage_times(self, reset=False):
         n = ctypes.c_int(64)

@@ -124,3 +124,93 @@ def test_not_converged_status(lib):
     with exacc.CCSD(eps, B, 4) as cc:
         st, steps, r, conv = cc.iterate(1)
         assert st == exacc.NOT_CONVERGED and steps == 1 and not conv and r > 0
+
+
+@pytest.mark.timeout(900)
+def test_full_size_residual_samples(lib):
+    """nocc=40, nvir=360, naux=1200 (the benchmark system, device inputs on a torch stream):
+    the GPU residual at random amplitudes vs the element-by-element oracle on a grid of
+    sampled entries, and the energy.  Tolerance: FP64 sums of up to P_v = 64,620 products,
+    1e-11 relative to the largest sampled |S|."""
+    import torch
+    from oracle.elements import ResidualElements
+    from paper_2103_08473_amd.exacc import CCSD
+    o, v, X = 40, 360, 1200
+    say("full-size case", o, v, X, ": generating inputs")
+    eps, B = make_system(o, v, X, seed=0)
+    t1, t2 = make_amplitudes(o, v, seed=1, scale=0.01)
+    say("  GPU residual")
+    eps_d = torch.from_numpy(eps).cuda()
+    B_d = torch.from_numpy(B).cuda()
+    stream = torch.cuda.Stream()
+    with CCSD(eps_d, B_d, o, stream=stream.cuda_stream, timing=1) as cc:
+        del B_d
+        cc.set_amplitudes(t1, t2)
+        g1, g2 = cc.residual()
+        ge = cc.energy()
+    say("  oracle entries")
+    el = ResidualElements(eps, B, o, t1, t2)
+    rng = np.random.default_rng(2024)
+    ij = [tuple(rng.choice(o, 2, replace=False)) for _ in range(3)] + [(0, o - 1)]
+    ab = [tuple(rng.choice(v, 2, replace=False)) for _ in range(4)] + [(0, v - 1), (v - 2, v - 1)]
+    ref, got = [], []
+    for (i, j) in ij:
+        for (a, b) in ab:
+            ref.append(el.S2(i, j, a, b))
+            got.append(g2[i, j, a, b])
+    say("  S2 samples done")
+    for (i, a) in [(0, 0), (o - 1, v - 1)] + [(int(rng.integers(o)), int(rng.integers(v))) for _ in range(6)]:
+        ref.append(el.S1(i, a))
+        got.append(g1[i, a])
+    ref, got = np.array(ref), np.array(got)
+    scale = np.abs(ref).max()
+    err = np.abs(ref - got).max()
+    say("  max |dS| %.3e  scale %.3e" % (err, scale))
+    assert scale > 0 and err <= 1e-11 * scale
+    assert np.abs(g2 + g2.transpose(1, 0, 2, 3)).max() <= 1e-14 * scale
+    assert abs(ge - el.energy()) <= 1e-10
+
+
+# ---------------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("o,v,X", [(10, 40, 120), (12, 70, 150), (1, 9, 20)])
+def test_fp32_phase_residual(lib, o, v, X):
+    """FP32 contractions, FP64 assembly: the residual agrees with the FP64 oracle to FP32
+    accuracy (sums of <= P_v products of unit roundoff 6e-8: 1e-5 of the largest |S|)."""
+    from paper_2103_08473_amd import exacc
+    say("fp32 residual case", o, v, X)
+    eps, B = make_system(o, v, X, seed=o * 1000 + v, sigma=0.2)
+    t1, t2 = make_amplitudes(o, v, seed=7 + o, scale=0.1)
+    S1, S2 = residual(eps, build_integrals(B, o), t1, t2)
+    with exacc.CCSD(eps, B, o, precision=exacc.MIXED_FP32) as cc:
+        assert cc.phase() == (True, 0)
+        cc.set_amplitudes(t1, t2)
+        g1, g2 = cc.residual()
+    scale = max(np.abs(S2).max() if S2.size else 0.0, np.abs(S1).max())
+    e1 = np.abs(g1 - S1).max() / scale
+    e2 = np.abs(g2 - S2).max() / scale if S2.size else 0.0
+    say("  rel err S1 %.2e S2 %.2e" % (e1, e2))
+    assert e1 <= 1e-5 and e2 <= 1e-5
+    assert e1 + e2 > 1e-12          # the FP32 phase really ran in FP32
+
+
+@pytest.mark.parametrize("o,v,X,seed", [(6, 40, 120, 2), (8, 48, 144, 3)])
+def test_mixed_precision_solve_matches_fp64_oracle(lib, o, v, X, seed):
+    """FP32 phase, switch below 1e-5, >= 3 FP64 iterations to 1e-10: |dE| <= 1e-7 Eh
+    against the converged FP64 oracle (and the amplitudes to 1e-7)."""
+    from paper_2103_08473_amd import exacc
+    say("mixed solve case", o, v, X, seed)
+    eps, B = make_system(o, v, X, seed=seed)
+    ref = oracle.solve(eps, B, o, max_iter=80, tol=1e-10)
+    assert ref.converged
+    phases = []
+    with exacc.CCSD(eps, B, o, precision=exacc.MIXED_FP32, tol=1e-10, max_iter=80) as cc:
+        e, conv, hist = cc.solve(callback=lambda it, E, r: phases.append(cc.phase()[0]))
+        t1, t2 = cc.amplitudes()
+        _, n64 = cc.phase()
+    assert conv and n64 >= 3
+    assert phases[0] is True and phases[-1] is False
+    dE = abs(e - ref.energy)
+    dT = max(np.abs(t1 - ref.t1).max(), np.abs(t2 - ref.t2).max())
+    say("  iterations %d (fp32 %d), |dE| %.2e Eh, max|dT| %.2e" % (len(hist), sum(phases) + 1, dE, dT))
+    assert dE <= 1e-7
+    assert dT <= 1e-7
