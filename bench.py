@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA = 78.6  # TFLOP/s, MI355X dense FP64 matrix
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
+PEAK_BF16_MFMA = 2516.6  # TFLOP/s, MI355X dense BF16 matrix
 WORKLOAD = dict(nocc=40, nvir=360, naux=1200, seed=0)
 
 
@@ -69,6 +70,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="first run one plain device-to-device copy of this many GiB (a known-size "
+                         "kernel to scale hardware byte counters by)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -82,6 +86,13 @@ def main():
     o, v, X = WORKLOAD["nocc"], WORKLOAD["nvir"], WORKLOAD["naux"]
     eps, B = make_system(o, v, X, seed=WORKLOAD["seed"])
     torch.cuda.set_device(0)
+    if args.copy_calibration_gib > 0:
+        nel = int(args.copy_calibration_gib * (1 << 30)) // 8
+        src_t = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
     eps_d = torch.from_numpy(eps).cuda()
     B_d = torch.from_numpy(B).cuda()
     stream = torch.cuda.Stream()
@@ -100,32 +111,38 @@ def main():
     E = cc.energy()
     cc.close()
 
-    mixed = None
+    mixed = {}
     if not args.no_mixed:
-        # same system, mixed precision: the FP32-contraction phase of the schedule
-        cm = exacc.CCSD(eps_d, B_d, o, stream=stream.cuda_stream, timing=1, tol=1e-9,
-                        precision=exacc.MIXED_FP32)
-        for _ in range(args.warmup):
-            cm.iterate(1)
-        cm.stage_times(reset=True)
-        assert cm.phase()[0]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            cm.iterate(1)
-        torch.cuda.synchronize()
-        dtm = (time.perf_counter() - t0) / args.steps
-        sm = cm.stage_times(reset=True)
-        cm.close()
-        bms = sm.get("ladder_build", float("nan")) / args.steps
-        mixed = {"phase": "fp32 contractions, fp64 assembly/DIIS/energy",
-                 "s_per_iter": round(dtm, 4),
-                 "ladder_tflops_per_iter": round(exacc.ladder_flops(o, v, X) / dtm / 1e12, 3),
-                 "speedup_vs_fp64": round((dt / args.steps) / dtm, 3),
-                 "ladder_build_tflops": round(ladder_build_flops(o, v, X) / (bms * 1e-3) / 1e12, 3),
-                 "ladder_build_frac_fp32_peak": round(ladder_build_flops(o, v, X) / (bms * 1e-3) / 1e12
-                                                      / PEAK_FP32_MFMA, 4),
-                 "stage_ms_per_iter": {k: round(t / args.steps, 2) for k, t in sm.items()}}
+        # same system, low-precision phases of the mixed schedules
+        for name, prec in (("mixed_fp32", exacc.MIXED_FP32), ("mixed_bf16x3", exacc.MIXED_BF16X3)):
+            cm = exacc.CCSD(eps_d, B_d, o, stream=stream.cuda_stream, timing=1, tol=1e-9,
+                            precision=prec)
+            for _ in range(args.warmup):
+                cm.iterate(1)
+            cm.stage_times(reset=True)
+            assert cm.phase()[0]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                cm.iterate(1)
+            torch.cuda.synchronize()
+            dtm = (time.perf_counter() - t0) / args.steps
+            sm = cm.stage_times(reset=True)
+            cm.close()
+            bms = sm.get("ladder_build", float("nan")) / args.steps
+            btf = ladder_build_flops(o, v, X) / (bms * 1e-3) / 1e12
+            mixed[name] = {
+                "phase": ("fp32" if prec == exacc.MIXED_FP32 else "bf16x3 ladder, fp32 other")
+                         + " contractions, fp64 assembly/DIIS/energy",
+                "s_per_iter": round(dtm, 4),
+                "ladder_tflops_per_iter": round(exacc.ladder_flops(o, v, X) / dtm / 1e12, 3),
+                "speedup_vs_fp64": round((dt / args.steps) / dtm, 3),
+                "ladder_build_tflops": round(btf, 3),
+                "stage_ms_per_iter": {k: round(t / args.steps, 2) for k, t in sm.items()}}
+            if prec == exacc.MIXED_FP32:
+                mixed[name]["ladder_build_frac_fp32_peak"] = round(btf / PEAK_FP32_MFMA, 4)
+            else:  # 9 bf16 MFMA products per complex multiply-add = 18 hardware flops
+                mixed[name]["ladder_build_hw_frac_bf16_peak"] = round(btf * 18 / 8 / PEAK_BF16_MFMA, 4)
     del B_d
 
     s_per_iter = dt / args.steps
@@ -164,8 +181,7 @@ def main():
                                       "kernel's 3-multiplication complex product issues 6",
                      "hw_frac": round(0.75 * achieved / PEAK_FP64_MFMA, 4)},
     }
-    if mixed is not None:
-        out["mixed_fp32"] = mixed
+    out.update(mixed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(eps, B, o)
     print(json.dumps(out), flush=True)

@@ -51,7 +51,14 @@ struct Gett {
 // Scratch the calling thread's GETT launches may use for split-K partials.
 void set_gett_workspace(void* p, size_t bytes);
 
-enum GettKind { GETT_GENERIC = 0, GETT_LADDER_BUILD = 1, GETT_LADDER_CONTRACT = 2, GETT_RING = 3 };
+enum GettKind {
+  GETT_GENERIC = 0,
+  GETT_LADDER_BUILD = 1,
+  GETT_LADDER_CONTRACT = 2,
+  GETT_RING = 3,
+  GETT_LADDER_BUILD_BF16X3 = 4,     // FP32 operands, BF16x3 products (falls back to FP32 MFMA
+  GETT_LADDER_CONTRACT_BF16X3 = 5   // when an operand is not K-contiguous)
+};
 
 template <typename R>
 void launch_gett(const Gett<R>& g, int kind, hipStream_t s);
@@ -77,9 +84,9 @@ void k_ladder_antisym(const T* Ta, T* W, int nb, int v, hipStream_t s);
 // S2 pieces of type T are summed in FP64 with the FP64 driver <ab||ij> and the
 // diagonal Fock part; writes the Jacobi step (or the full residual into s2_full).
 template <typename T>
-void k_assemble_t2(const T* Znp, const T* Zab, const T* Zij, const T* R, const double* Voovv_p,
-                   const double* t2p, const double* eps, int o, int v, double shift, double* xt,
-                   double* e, double* s2_full, double* partial, int nblk, hipStream_t s);
+void k_assemble_t2(const T* Znp, const T* Z, const T* R, const double* Voovv_p, const double* t2p,
+                   const double* eps, int o, int v, double shift, double* xt, double* e,
+                   double* s2_full, double* partial, int nblk, hipStream_t s);
 template <typename T>
 void k_assemble_t1(const T* S1, const double* t1, const double* eps, int o, int v, double shift,
                    double* xt, double* e, double* s1_full, double* partial, hipStream_t s);

@@ -220,24 +220,48 @@ __global__ void expand_c_kernel(const T* __restrict__ Vooov, const T* __restrict
   }
 }
 
-// W[b'][x=(c<d)] = Ta[c][b'][d] - Ta[d][b'][c]
+// W[b'][x=(c<d)] = Ta[c][b'][d] - Ta[d][b'][c].  One block per (b', c-tile, d-tile) with
+// c-tile <= d-tile: both Ta tiles are read along their contiguous last index and
+// the second is transposed through LDS, so every global access is coalesced.
 template <typename T>
 __global__ void ladder_antisym_kernel(const T* __restrict__ Ta, T* __restrict__ W, int nb, int v) {
-  const int64_t Pv = (int64_t)v * (v - 1) / 2, tot = (int64_t)nb * Pv;
-  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
-    const int64_t bp = t / Pv, x = t - bp * Pv;
-    int c, d;
-    pair_of(x, v, c, d);
-    const z p = ld(Ta, ((int64_t)c * nb + bp) * v + d);
-    const z q = ld(Ta, ((int64_t)d * nb + bp) * v + c);
-    st(W, t, sub(p, q));
+  __shared__ double tr[32][33], ti[32][33];
+  const int ntile = (v + 31) / 32;
+  // blockIdx.x enumerates tile pairs (tc <= td) row-major
+  int tc = 0, rem = blockIdx.x;
+  while (rem >= ntile - tc) {
+    rem -= ntile - tc;
+    ++tc;
+  }
+  const int td = tc + rem;
+  const int64_t bp = blockIdx.y;
+  const int64_t Pv = (int64_t)v * (v - 1) / 2;
+  const int c0 = 32 * tc, d0 = 32 * td;
+  const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+  // stage Ta[d][b'][c] for d in d-tile, c in c-tile (contiguous in c) as [c - c0][d - d0]
+  for (int r = ty; r < 32; r += 8) {
+    const int d = d0 + r, c = c0 + tx;
+    if (d < v && c < v) {
+      const z q = ld(Ta, ((int64_t)d * nb + bp) * v + c);
+      tr[tx][r] = q.x;
+      ti[tx][r] = q.y;
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int c = c0 + r, d = d0 + tx;
+    if (c < v && d < v && c < d) {
+      const z p = ld(Ta, ((int64_t)c * nb + bp) * v + d);
+      const z q{tr[r][tx], ti[r][tx]};
+      st(W, bp * Pv + pidx(c, d, v), sub(p, q));
+    }
   }
 }
 
 // Residual assembly + Jacobi step for the doubles (packed i<j, a<b).
 template <typename T>
-__global__ void assemble_t2_kernel(const T* __restrict__ Znp, const T* __restrict__ Zab,
-                                   const T* __restrict__ Zij, const T* __restrict__ R,
+__global__ void assemble_t2_kernel(const T* __restrict__ Znp, const T* __restrict__ Z,
+                                   const T* __restrict__ R,
                                    const double* __restrict__ Vp, const double* __restrict__ t2p,
                                    const double* __restrict__ eps, int o, int v, double shift,
                                    double* __restrict__ xt, double* __restrict__ e,
@@ -254,9 +278,7 @@ __global__ void assemble_t2_kernel(const T* __restrict__ Znp, const T* __restric
     const int64_t ijba = ((int64_t)i * o + j) * vv + (int64_t)b * v + a;
     const int64_t jiab = ((int64_t)j * o + i) * vv + (int64_t)a * v + b;
     const int64_t jiba = ((int64_t)j * o + i) * vv + (int64_t)b * v + a;
-    z s = ld(Znp, t);
-    s = add(s, sub(ld(Zab, ijab), ld(Zab, ijba)));
-    s = add(s, sub(ld(Zij, ijab), ld(Zij, jiab)));
+    z s = add(ld(Znp, t), ld(Z, ijab));
     s = add(s, add(sub(ld(R, ijab), ld(R, jiab)), sub(ld(R, jiba), ld(R, ijba))));
     z g = ld(Vp, t);
     s.x += g.x;
@@ -511,9 +533,11 @@ void k_expand_c(const T* Vooov, const T* Cp, T* Cf, int o, int v, hipStream_t s)
 
 template <typename T>
 void k_ladder_antisym(const T* Ta, T* W, int nb, int v, hipStream_t s) {
-  const int64_t tot = (int64_t)nb * ((int64_t)v * (v - 1) / 2);
-  if (tot <= 0) return;
-  hipLaunchKernelGGL(ladder_antisym_kernel<T>, dim3(nblocks(tot)), dim3(TB), 0, s, Ta, W, nb, v);
+  if (nb <= 0 || v < 2) return;
+  const int nt = (v + 31) / 32;
+  if (nb > 65535) raise(-5, "ladder row too long");
+  dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)nb), block(32, 8);
+  hipLaunchKernelGGL(ladder_antisym_kernel<T>, grid, block, 0, s, Ta, W, nb, v);
   HIPCHECK(hipGetLastError());
 }
 
@@ -522,11 +546,11 @@ int dot_many_blocks(int64_t len) { return nblocks(len, 2048); }
 int energy_blocks(int64_t npairs) { return nblocks(npairs, 2048); }
 
 template <typename T>
-void k_assemble_t2(const T* Znp, const T* Zab, const T* Zij, const T* R, const double* Voovv_p,
-                   const double* t2p, const double* eps, int o, int v, double shift, double* xt,
-                   double* e, double* s2_full, double* partial, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL(assemble_t2_kernel<T>, dim3(nblk), dim3(TB), 0, s, Znp, Zab, Zij, R, Voovv_p, t2p,
-                     eps, o, v, shift, xt, e, s2_full, partial);
+void k_assemble_t2(const T* Znp, const T* Z, const T* R, const double* Voovv_p, const double* t2p,
+                   const double* eps, int o, int v, double shift, double* xt, double* e,
+                   double* s2_full, double* partial, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(assemble_t2_kernel<T>, dim3(nblk), dim3(TB), 0, s, Znp, Z, R, Voovv_p, t2p, eps,
+                     o, v, shift, xt, e, s2_full, partial);
   HIPCHECK(hipGetLastError());
 }
 
@@ -594,9 +618,9 @@ void k_pack_amplitudes(const double* t1, const double* t2, double* x, int o, int
   template void k_ring_operands<T>(const T*, const double*, T*, T*, int, int, hipStream_t);      \
   template void k_expand_c<T>(const T*, const T*, T*, int, int, hipStream_t);                    \
   template void k_ladder_antisym<T>(const T*, T*, int, int, hipStream_t);                        \
-  template void k_assemble_t2<T>(const T*, const T*, const T*, const T*, const double*,          \
-                                 const double*, const double*, int, int, double, double*,        \
-                                 double*, double*, double*, int, hipStream_t);                   \
+  template void k_assemble_t2<T>(const T*, const T*, const T*, const double*, const double*,     \
+                                 const double*, int, int, double, double*, double*, double*,     \
+                                 double*, int, hipStream_t);                                      \
   template void k_assemble_t1<T>(const T*, const double*, const double*, int, int, double,       \
                                  double*, double*, double*, double*, hipStream_t);
 EXACC_INST(double)

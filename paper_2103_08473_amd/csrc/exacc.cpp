@@ -71,52 +71,36 @@ static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
   p.nslots = std::max(1, op.diis_size);
   const int64_t rowbytes = std::max<int64_t>(1, p.Pv) * 16;
   int64_t cp = op.ladder_chunk_pairs;
-  if (cp <= 0) cp = std::max<int64_t>(v, (int64_t)(8ll << 30) / rowbytes);
+  if (cp <= 0) cp = std::max<int64_t>(v, (int64_t)(2ll << 30) / rowbytes);
   cp = std::min<int64_t>(std::max<int64_t>(cp, std::max(1, v - 1)), std::max<int64_t>(1, p.Pv));
   p.chunk_pairs = cp;
   const int64_t vovv_row = (int64_t)o * v * v;  // per b
   p.vovv_chunk = std::max<int64_t>(1, std::min<int64_t>(v, (int64_t)(2ll << 30) / (16 * vovv_row)));
   const int64_t n = p.n, oo = (int64_t)o * o;
-  auto add = [&](const char* nm, int64_t e, bool tr = false) { p.items.push_back({nm, e, tr}); };
-  add("Bt", n * n * X);
-  add("Voooo", oo * oo);
-  add("Vooov", oo * o * v);
-  add("Voovv", p.oovv);
-  add("Voovv_p", p.Po * p.Pv);
-  add("Vvovo", p.oovv);
-  add("Vvovv_p", (int64_t)v * o * p.Pv);
-  add("x", p.L);
-  add("diis", 2 * p.nslots * p.L);
-  add("T2", p.oovv);
-  add("TAU", p.oovv);
-  add("taup", p.Po * p.Pv);
-  add("Tq", p.oovv);
-  add("Xp", p.oovv);
-  add("H4", p.oovv);
-  add("R", p.oovv);
-  add("Zij", p.oovv);
-  add("Zab", p.oovv);
-  add("Znp", p.Po * p.Pv);
-  add("small", 2 * p.vv + 3 * oo + 2 * (int64_t)o * v + X + p.vv * X + oo * X + 2 * (int64_t)v * o * X +
-                   p.Po * v * o + oo * v * o + oo * oo + p.Po * p.Po);
-  add("Ta", (int64_t)v * std::max(1, v - 1) * v);
-  add("W", p.chunk_pairs * std::max<int64_t>(1, p.Pv));
-  add("splitk_ws", (256ll << 20) / 16);
-  if (op.precision == EXACC_MIXED_FP32)  // FP32 copies of B and the stored classes
-    add("fp32_copies", (n * n * X + oo * oo + oo * o * v + 2 * p.oovv + (int64_t)v * o * p.Pv + 1) / 2);
-  add("Braw", n * n * X, true);
-  add("vovv_tmp", p.vovv_chunk * vovv_row, true);
-  size_t pers = 0, tr = 0;
-  for (auto& it : p.items) {
-    const size_t b = (size_t)it.elems * 16 + 256;
-    if (it.transient)
-      tr = std::max(tr, b);
-    else
-      pers += b;
-  }
-  pers += 1 << 20;  // reductions, tables, eps
-  p.bytes_persistent = pers;
-  p.bytes_peak = pers + tr + (size_t)(n * n * X) * 16;  // Braw and vovv_tmp not live together
+  const bool mixed = op.precision != EXACC_FP64;
+  // bytes of each buffer class (16 bytes per complex element, +256 alignment slack)
+  auto B16 = [](int64_t e) { return (size_t)std::max<int64_t>(e, 1) * 16 + 256; };
+  const size_t common = B16(n * n * X)                          // Bt
+                        + B16(oo * oo) + B16(oo * o * v)         // Voooo, Vooov
+                        + B16(p.Po * p.Pv)                       // Voovv_p
+                        + B16(p.L) + B16(2 * p.nslots * p.L)     // x, DIIS
+                        + 5 * B16(p.oovv)                        // TAU, Tq, Xp/R, H4, Z
+                        + 2 * B16(p.Po * p.Pv)                   // taup, Znp
+                        + B16(2 * p.vv + 3 * oo + 3 * (int64_t)o * v + X + oo * X +
+                              2 * (int64_t)v * o * X + p.Po * v * o + oo * v * o + oo * oo +
+                              p.Po * p.Po)                       // small intermediates
+                        + B16((int64_t)v * std::max(1, v - 1) * v)  // Ta
+                        + B16(p.chunk_pairs * std::max<int64_t>(1, p.Pv))  // W
+                        + (256u << 20) + (2u << 20);             // split-K, reductions
+  const size_t big64 = B16(p.oovv) + B16((int64_t)v * o * p.Pv);  // Voovv, Vvovv_p (FP64)
+  const size_t big32 = (B16(p.oovv) + B16((int64_t)v * o * p.Pv) + B16(n * n * X) + B16(oo * oo) +
+                        B16(oo * o * v)) / 2;                     // FP32 copies
+  const size_t vovv_tmp = B16(p.vovv_chunk * vovv_row) + B16(p.vovv_chunk * o * p.Pv);
+  const size_t create_peak = B16(n * n * X) * 2 + B16(p.oovv) + big32 + vovv_tmp;  // staging
+  const size_t phase64 = common + big64 + vovv_tmp;
+  const size_t phase32 = common + big32;
+  p.bytes_persistent = mixed ? phase32 : common + big64;
+  p.bytes_peak = std::max(create_peak, mixed ? std::max(phase32, phase64) : phase64);
   return p;
 }
 
@@ -153,13 +137,16 @@ struct Handle {
   std::vector<void*> allocs;
   std::vector<AllocRange> ranges;  // allocs with sizes, for the planner's extent check
   double* eps = nullptr;
-  double *Bt = nullptr, *Voooo, *Vooov, *Voovv, *Voovv_p, *Vvovo, *Vvovv_p;
-  double *x, *diis, *T2, *TAU, *taup, *Tq, *Xp, *H4, *R, *Zij, *Zab, *Znp;
-  double *Hac, *Gac, *Hki, *Gki, *Hkc, *y, *Zt, *U, *Vt, *M1, *Y, *S1, *Cp, *Cf, *Af, *Ap;
+  // Voovv and Vvovv_p exist in FP64 only while FP64 contractions are in use
+  double *Bt = nullptr, *Voooo, *Vooov, *Voovv = nullptr, *Voovv_p, *Vvovv_p = nullptr;
+  // Xp is reused for the ring output R once the ring intermediate is built;
+  // Z holds the doubles residual pieces that carry no permutation operator
+  double *x, *diis, *TAU, *taup, *Tq, *Xp, *H4, *Z, *Znp;
+  double *Hac, *Gac, *Hki, *Gki, *Hkc, *y, *U, *Vt, *M1, *Y, *S1, *Cp, *Cf, *Af, *Ap;
   double *Ta, *W, *t1w;
   // FP32 copies of B and the stored integral classes (mixed precision only)
   float *Bt32 = nullptr, *Voooo32 = nullptr, *Vooov32 = nullptr, *Voovv32 = nullptr,
-        *Vvovo32 = nullptr, *Vvovv_p32 = nullptr;
+        *Vvovv_p32 = nullptr;
   bool phase32 = false;       // current iteration runs its contractions in FP32
   bool last32 = false;        // the last completed iteration ran in FP32
   int fp64_iters = 0;         // FP64 iterations since the last switch
@@ -189,6 +176,23 @@ struct Handle {
   void use() {
     set_alloc_registry(ranges.data(), (int)ranges.size());
     set_gett_workspace(ws, ws_bytes);
+  }
+  template <typename T>
+  void dfree(T*& p) {
+    if (!p) return;
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i] == (void*)p) {
+        allocs.erase(allocs.begin() + i);
+        break;
+      }
+    for (size_t i = 0; i < ranges.size(); ++i)
+      if (ranges[i].base == (const void*)p) {
+        ranges.erase(ranges.begin() + i);
+        break;
+      }
+    HIPCHECK(hipFree(p));
+    p = nullptr;
+    use();
   }
   double* dalloc(int64_t complex_elems) {
     void* p = nullptr;
@@ -238,27 +242,27 @@ static const cplx ONE{1, 0}, MONE{-1, 0}, HALF{0.5, 0};
 // FP32 integral copies; the work arrays alias the FP64 buffers (half their size).
 template <typename R>
 struct Work {
-  R *Bt, *Voooo, *Vooov, *Voovv, *Vvovo, *Vvovv_p;
-  R *T2, *TAU, *taup, *Tq, *Xp, *H4, *R_, *Zij, *Zab, *Znp;
-  R *Hac, *Gac, *Hki, *Gki, *Hkc, *y, *Zt, *U, *Vt, *M1, *Y, *S1, *Cp, *Cf, *Af, *Ap, *Ta, *W;
+  R *Bt, *Voooo, *Vooov, *Voovv, *Vvovv_p;
+  R *TAU, *taup, *Tq, *Xp, *H4, *R_, *Z, *Znp;
+  R *Hac, *Gac, *Hki, *Gki, *Hkc, *y, *U, *Vt, *M1, *Y, *S1, *Cp, *Cf, *Af, *Ap, *Ta, *W;
   R* t1;  // t1 in R, as a contraction operand
 };
 template <typename R>
 static Work<R> work(Handle& h);
 template <>
 Work<double> work<double>(Handle& h) {
-  return Work<double>{h.Bt, h.Voooo, h.Vooov, h.Voovv, h.Vvovo, h.Vvovv_p, h.T2, h.TAU, h.taup,
-                      h.Tq, h.Xp, h.H4, h.R, h.Zij, h.Zab, h.Znp, h.Hac, h.Gac, h.Hki, h.Gki,
-                      h.Hkc, h.y, h.Zt, h.U, h.Vt, h.M1, h.Y, h.S1, h.Cp, h.Cf, h.Af, h.Ap, h.Ta, h.W,
+  return Work<double>{h.Bt, h.Voooo, h.Vooov, h.Voovv, h.Vvovv_p, h.TAU, h.taup,
+                      h.Tq, h.Xp, h.H4, h.Xp, h.Z, h.Znp, h.Hac, h.Gac, h.Hki, h.Gki,
+                      h.Hkc, h.y, h.U, h.Vt, h.M1, h.Y, h.S1, h.Cp, h.Cf, h.Af, h.Ap, h.Ta, h.W,
                       h.t1w};
 }
 template <>
 Work<float> work<float>(Handle& h) {
   auto f = [](double* p) { return reinterpret_cast<float*>(p); };
-  return Work<float>{h.Bt32, h.Voooo32, h.Vooov32, h.Voovv32, h.Vvovo32, h.Vvovv_p32,
-                     f(h.T2), f(h.TAU), f(h.taup), f(h.Tq), f(h.Xp), f(h.H4), f(h.R), f(h.Zij),
-                     f(h.Zab), f(h.Znp), f(h.Hac), f(h.Gac), f(h.Hki), f(h.Gki), f(h.Hkc),
-                     f(h.y), f(h.Zt), f(h.U), f(h.Vt), f(h.M1), f(h.Y), f(h.S1), f(h.Cp),
+  return Work<float>{h.Bt32, h.Voooo32, h.Vooov32, h.Voovv32, h.Vvovv_p32,
+                     f(h.TAU), f(h.taup), f(h.Tq), f(h.Xp), f(h.H4), f(h.Xp), f(h.Z),
+                     f(h.Znp), f(h.Hac), f(h.Gac), f(h.Hki), f(h.Gki), f(h.Hkc),
+                     f(h.y), f(h.U), f(h.Vt), f(h.M1), f(h.Y), f(h.S1), f(h.Cp),
                      f(h.Cf), f(h.Af), f(h.Ap), f(h.Ta), f(h.W), f(h.t1w)};
 }
 
@@ -285,48 +289,78 @@ static void dcopy(Handle& h, R* dst, const R* src, int64_t celems) {
 }
 
 
-// ------------------------------------------------------------------ integrals (create)
-static void build_integrals(Handle& h, double* vovv_tmp) {
-  Scope sc(h, "integrals");
+// ------------------------------------------------------------------ integrals
+// <kl||ij> = (ki|lj) - (kj|li) and <kl||ic> = (ki|lc) - (kc|li) (FP64, small)
+static void build_oooo_ooov(Handle& h) {
   const int o = h.P.o, v = h.P.v;
   const hipStream_t s = h.s;
   Views<double> b = bviews(h, h.Bt);
-  // <kl||ij> = (ki|lj) - (kj|li)
   auto Voooo = view(h.Voooo, {o, o, o, o});
   contract(s, "kiP,ljP->klij", ONE, b.Boo, b.Boo, false, Voooo);
   contract(s, "kjP,liP->klij", MONE, b.Boo, b.Boo, true, Voooo);
-  // <kl||ic> = (ki|lc) - (kc|li)
   auto Vooov = view(h.Vooov, {o, o, o, v});
   contract(s, "kiP,lcP->klic", ONE, b.Boo, b.Bov, false, Vooov);
   contract(s, "kcP,liP->klic", MONE, b.Bov, b.Boo, true, Vooov);
-  // <kl||cd> = (kc|ld) - (kd|lc)
-  auto Voovv = view(h.Voovv, {o, o, v, v});
-  contract(s, "kcP,ldP->klcd", ONE, b.Bov, b.Bov, false, Voovv);
-  contract(s, "kdP,lcP->klcd", MONE, b.Bov, b.Bov, true, Voovv);
-  // <ak||ci> = (ac|ki) - (ai|kc), stored as [a][i][k][c]
-  auto Vvovo = view(h.Vvovo, {v, o, o, v});
-  contract(s, "acP,kiP->aikc", ONE, b.Bvv, b.Boo, false, Vvovo);
-  contract(s, "aiP,kcP->aikc", MONE, b.Bvo, b.Bov, true, Vvovo);
-  // packed <ij||ab>, i<j, a<b
-  if (h.P.Po > 0) k_pack_last2(h.Voovv_p, h.Voovv, h.rowmap_o, h.P.Po, v, h.P.vv, s);
-  // <bk||cd> = (bc|kd) - (bd|kc), packed over c<d, rows (b, k); built in chunks of b
-  if (h.P.Pv > 0) {
-    const int64_t nX = (int64_t)h.P.n * h.P.X;
-    for (int b0 = 0; b0 < v; b0 += (int)h.P.vovv_chunk) {
-      const int nb = (int)std::min<int64_t>(h.P.vovv_chunk, v - b0);
-      auto Bc = sview(b.Bvv.p + 2 * (int64_t)b0 * nX, {nb, v, h.P.X}, {nX, h.P.X, 1});
-      auto tmp = view(vovv_tmp, {nb, o, v, v});
-      contract(s, "bcP,kdP->bkcd", ONE, Bc, b.Bov, false, tmp);
-      contract(s, "bdP,kcP->bkcd", MONE, Bc, b.Bov, true, tmp);
-      k_pack_last2(h.Vvovv_p + 2 * (int64_t)b0 * o * h.P.Pv, vovv_tmp, nullptr, (int64_t)nb * o, v,
-                   h.P.vv, s);
+}
+
+// <kl||cd> = (kc|ld) - (kd|lc), full [k][l][c][d] FP64
+static void build_oovv(Handle& h, double* dst) {
+  const int o = h.P.o, v = h.P.v;
+  Views<double> b = bviews(h, h.Bt);
+  auto V = view(dst, {o, o, v, v});
+  contract(h.s, "kcP,ldP->klcd", ONE, b.Bov, b.Bov, false, V);
+  contract(h.s, "kdP,lcP->klcd", MONE, b.Bov, b.Bov, true, V);
+}
+
+// <bk||cd> = (bc|kd) - (bd|kc) packed over c<d, rows (b, k), built in chunks of b
+// from the FP64 factors; T = float rounds each packed chunk into the FP32 copy.
+template <typename T>
+static void build_vovv_packed(Handle& h, T* dst) {
+  const int o = h.P.o, v = h.P.v;
+  if (h.P.Pv == 0) return;
+  Views<double> b = bviews(h, h.Bt);
+  const int64_t nX = (int64_t)h.P.n * h.P.X;
+  const int64_t tmp_e = h.P.vovv_chunk * o * h.P.vv, stage_e = h.P.vovv_chunk * o * h.P.Pv;
+  double* tmp = h.dalloc(tmp_e);
+  double* stage = sizeof(T) == sizeof(double) ? nullptr : h.dalloc(stage_e);
+  for (int b0 = 0; b0 < v; b0 += (int)h.P.vovv_chunk) {
+    const int nb = (int)std::min<int64_t>(h.P.vovv_chunk, v - b0);
+    auto Bc = sview(b.Bvv.p + 2 * (int64_t)b0 * nX, {nb, v, h.P.X}, {nX, h.P.X, 1});
+    auto t = view(tmp, {nb, o, v, v});
+    contract(h.s, "bcP,kdP->bkcd", ONE, Bc, b.Bov, false, t);
+    contract(h.s, "bdP,kcP->bkcd", MONE, Bc, b.Bov, true, t);
+    const int64_t rows = (int64_t)nb * o, off = (int64_t)b0 * o * h.P.Pv;
+    if (stage) {
+      k_pack_last2<double>(stage, tmp, nullptr, rows, v, h.P.vv, h.s);
+      k_cast(stage, reinterpret_cast<float*>(dst) + 2 * off, 2 * rows * h.P.Pv, h.s);
+    } else {
+      k_pack_last2<double>(reinterpret_cast<double*>(dst) + 2 * off, tmp, nullptr, rows, v, h.P.vv, h.s);
     }
   }
+  HIPCHECK(hipStreamSynchronize(h.s));
+  h.dfree(tmp);
+  h.dfree(stage);
+}
+
+// FP64 classes for FP64 contractions (mixed modes: at the switch; the FP32 copies go)
+static void ensure_fp64_classes(Handle& h) {
+  if (h.Voovv && h.Vvovv_p) return;
+  Scope sc(h, "switch_to_fp64");
+  h.dfree(h.Bt32);
+  h.dfree(h.Voooo32);
+  h.dfree(h.Vooov32);
+  h.dfree(h.Voovv32);
+  h.dfree(h.Vvovv_p32);
+  h.Voovv = h.dalloc(h.P.oovv);
+  build_oovv(h, h.Voovv);
+  h.Vvovv_p = h.dalloc((int64_t)h.P.v * h.P.o * h.P.Pv);
+  build_vovv_packed<double>(h, h.Vvovv_p);
 }
 
 // ------------------------------------------------------------------ residual pieces
 // Fills S1 (singles, without the diagonal Fock part) and the doubles pieces
-// Znp (no permutation), Zab (P_ab), Zij (P_ij), R (P_ij P_ab) for the
+// Znp (packed) and Z (full) with no permutation left to apply, and R which
+// still needs P_ij P_ab (applied in the assembly), for the
 // amplitudes in h.x.
 template <typename R>
 static void compute_residual(Handle& h) {
@@ -338,21 +372,25 @@ static void compute_residual(Handle& h) {
   const double* t1p = h.x;
   const double* t2p = h.x + 2 * (int64_t)o * v;
   auto t1 = view(w.t1, {o, v});
-  auto T2 = view(w.T2, {o, o, v, v});
+  // T2[i][k][a][b] read through the permuted copy Tq[b][i][k][a]
+  const int64_t ov = (int64_t)o * v, oov = (int64_t)o * o * v;
+  auto T2 = sview(w.Tq, {o, o, v, v}, {ov, v, 1, oov});
   auto TAU = view(w.TAU, {o, o, v, v});
   auto taup = view(w.taup, {Po, Pv});
   auto Voovv = view(w.Voovv, {o, o, v, v});
   auto Vooov = view(w.Vooov, {o, o, o, v});
-  auto Vvovo = view(w.Vvovo, {v, o, o, v});
   {
     Scope sc(h, "prep");
     if (sizeof(R) == sizeof(double))
       dcopy(h, (double*)w.t1, h.x, (int64_t)o * v);
     else
       k_cast(h.x, (float*)w.t1, 2 * (int64_t)o * v, s);
-    k_unpack_tau<R>(t1p, t2p, w.T2, w.TAU, w.taup, o, v, s);
-    k_ring_operands<R>(w.T2, t1p, w.Tq, w.Xp, o, v, s);
+    // full T2 goes to Z as scratch: Z is first written after Tq and Xp exist
+    k_unpack_tau<R>(t1p, t2p, w.Z, w.TAU, w.taup, o, v, s);
+    k_ring_operands<R>(w.Z, t1p, w.Tq, w.Xp, o, v, s);
   }
+  auto U = view(w.U, {o, o, X});
+  auto Vt = view(w.Vt, {v, o, X});
   auto Hac = view(w.Hac, {v, v}), Gac = view(w.Gac, {v, v});
   auto Hki = view(w.Hki, {o, o}), Gki = view(w.Gki, {o, o});
   auto Hkc = view(w.Hkc, {o, v});
@@ -363,23 +401,24 @@ static void compute_residual(Handle& h) {
     contract(s, "klcd,ld->kc", ONE, Voovv, t1, false, Hkc);
     dcopy(h, w.Gac, w.Hac, (int64_t)v * v);
     dcopy(h, w.Gki, w.Hki, (int64_t)o * o);
-    // sum_kd <ak||cd> t_k^d = sum_P B_ac^P (sum_kd B_kd^P t_k^d) - sum_Pd B_ad^P (sum_k t_k^d B_kc^P)
+    // DF t1 intermediates: y^P = sum_kd B^P_kd t_k^d, U^P_ki = sum_d B^P_kd t_i^d,
+    // Vt^P_ai = sum_c B^P_ac t_i^c
     auto y = view(w.y, {X});
     contract(s, "kdP,kd->P", ONE, b.Bov, t1, false, y);
+    contract(s, "kdP,id->kiP", ONE, b.Bov, t1, false, U);
+    contract(s, "acP,ic->aiP", ONE, b.Bvv, t1, false, Vt);
+    // sum_kd <ak||cd> t_k^d = sum_kd (ac|kd) t_k^d - sum_kd (ad|kc) t_k^d
+    //                       = sum_P B^P_ac y^P - sum_kP Vt^P_ak B^P_kc
     contract(s, "acP,P->ac", ONE, b.Bvv, y, true, Gac);
-    auto Zt = view(w.Zt, {v, v, X});
-    contract(s, "kd,kcP->dcP", ONE, t1, b.Bov, false, Zt);
-    contract(s, "adP,dcP->ac", MONE, b.Bvv, Zt, true, Gac);
+    contract(s, "akP,kcP->ac", MONE, Vt, b.Bov, true, Gac);
     contract(s, "klic,lc->ki", MONE, Vooov, t1, true, Gki);
   }
   auto H4 = view(w.H4, {v, o, o, v});
-  auto U = view(w.U, {o, o, X});
-  auto Vt = view(w.Vt, {v, o, X});
   {
     Scope sc(h, "ring_build");
-    dcopy(h, w.H4, w.Vvovo, h.P.oovv);
-    contract(s, "kdP,id->kiP", ONE, b.Bov, t1, false, U);
-    contract(s, "acP,ic->aiP", ONE, b.Bvv, t1, false, Vt);
+    // <ak||ci> = (ac|ki) - (ai|kc), formed from the factors each iteration
+    contract(s, "acP,kiP->aikc", ONE, b.Bvv, b.Boo, false, H4);
+    contract(s, "aiP,kcP->aikc", MONE, b.Bvo, b.Bov, true, H4);
     contract(s, "acP,kiP->aikc", ONE, b.Bvv, U, true, H4);
     contract(s, "aiP,kcP->aikc", MONE, Vt, b.Bov, true, H4);
     contract(s, "klic,la->aikc", MONE, Vooov, t1, true, H4);
@@ -391,12 +430,18 @@ static void compute_residual(Handle& h) {
     contract(s, "aikc,bjkc->ijab", ONE, H4, view(w.Tq, {v, o, o, v}), false, Rv, GETT_RING);
     contract(s, "aiP,bjP->ijab", ONE, Vt, b.Bvo, true, Rv);
   }
-  auto Zij = view(w.Zij, {o, o, v, v});
-  auto Zab = view(w.Zab, {o, o, v, v});
+  // Z and its views with i<->j or a<->b swapped: a term X launched into Z and,
+  // negated, into a swapped view accumulates P^-_ij X (or P^-_ab X) directly
+  const int64_t vv = (int64_t)v * v, ovv = (int64_t)o * v * v;
+  auto Z = view(w.Z, {o, o, v, v});
+  auto Zji = sview(w.Z, {o, o, v, v}, {vv, ovv, v, 1});
+  auto Zba = sview(w.Z, {o, o, v, v}, {ovv, vv, 1, v});
   {
     Scope sc(h, "fock_terms");
-    contract(s, "kj,ikab->ijab", ONE, Gki, T2, false, Zij);
-    contract(s, "ac,ijcb->ijab", ONE, Gac, T2, false, Zab);
+    contract(s, "kj,ikab->ijab", ONE, Gki, T2, false, Z);
+    contract(s, "kj,ikab->ijab", MONE, Gki, T2, true, Zji);
+    contract(s, "ac,ijcb->ijab", ONE, Gac, T2, true, Z);
+    contract(s, "ac,ijcb->ijab", MONE, Gac, T2, true, Zba);
   }
   {
     Scope sc(h, "cterm");
@@ -404,9 +449,17 @@ static void compute_residual(Handle& h) {
     contract(s, "bkx,px->pbk", MONE, view(w.Vvovv_p, {v, o, Pv}), taup, false, Cp);
     k_expand_c<R>(w.Vooov, w.Cp, w.Cf, o, v, s);
     auto Cf = view(w.Cf, {o, o, v, o});
-    contract(s, "bikc,jc->ijbk", ONE, Vvovo, t1, true, Cf);
-    contract(s, "bjkc,ic->ijbk", MONE, Vvovo, t1, true, Cf);
-    contract(s, "ijak,kb->ijab", ONE, Cf, t1, true, Zab);
+    // P^-_ij sum_c <bk||ci> t_j^c with <bk||ci> = (bc|ki) - (bi|kc):
+    //   sum_c (bc|ki) t_j^c = sum_P Vt^P_bj B^P_ki,  sum_c (bi|kc) t_j^c = sum_P B^P_bi U^P_kj
+    const int64_t vo = (int64_t)v * o, oo = (int64_t)o * o, oovo = oo * v * o;
+    auto Cfji = sview(w.Cf, {o, o, v, o}, {vo, o * vo, o, 1});
+    contract(s, "bjP,kiP->ijbk", ONE, Vt, b.Boo, true, Cf);
+    contract(s, "biP,kjP->ijbk", MONE, b.Bvo, U, true, Cf);
+    contract(s, "bjP,kiP->ijbk", MONE, Vt, b.Boo, true, Cfji);
+    contract(s, "biP,kjP->ijbk", ONE, b.Bvo, U, true, Cfji);
+    (void)oovo;
+    contract(s, "ijak,kb->ijab", ONE, Cf, t1, true, Z);
+    contract(s, "ijak,kb->ijab", MONE, Cf, t1, true, Zba);
   }
   auto Znp = view(w.Znp, {Po, Pv});
   {
@@ -420,6 +473,10 @@ static void compute_residual(Handle& h) {
     contract(s, "qp,qx->px", ONE, view(w.Ap, {Po, Po}), taup, false, Znp);
   }
   // particle ladder: Znp[ij][ab] += sum_{c<d} tau[ij][cd] <ab||cd>, <ab||cd> = (ac|bd) - (ad|bc)
+  // (BF16x3 products in the low-precision phase of the BF16x3 mode)
+  const bool bf = sizeof(R) == sizeof(float) && h.op.precision == EXACC_MIXED_BF16X3;
+  const int lad_build = bf ? GETT_LADDER_BUILD_BF16X3 : GETT_LADDER_BUILD;
+  const int lad_contract = bf ? GETT_LADDER_CONTRACT_BF16X3 : GETT_LADDER_CONTRACT;
   if (Po > 0 && Pv > 0) {
     const int64_t nX = (int64_t)h.P.n * X;
     int64_t rows = 0, start = 0;
@@ -428,7 +485,7 @@ static void compute_residual(Handle& h) {
       Scope sc(h, "ladder_contract");
       auto Wv = view(w.W, {rows, Pv});
       auto Zc = sview(w.Znp + 2 * start, {Po, rows}, {Pv, 1});
-      contract(s, "py,xy->px", ONE, taup, Wv, true, Zc, GETT_LADDER_CONTRACT);
+      contract(s, "py,xy->px", ONE, taup, Wv, true, Zc, lad_contract);
       start += rows;
       rows = 0;
     };
@@ -439,7 +496,7 @@ static void compute_residual(Handle& h) {
         Scope sc(h, "ladder_build");
         auto Ba = sview(b.Bvv.p + 2 * (int64_t)a * nX, {v, X}, {X, 1});
         auto Bb = sview(b.Bvv.p + 2 * (int64_t)(a + 1) * nX, {nb, v, X}, {nX, X, 1});
-        contract(s, "cP,bdP->cbd", ONE, Ba, Bb, false, view(w.Ta, {v, nb, v}), GETT_LADDER_BUILD);
+        contract(s, "cP,bdP->cbd", ONE, Ba, Bb, false, view(w.Ta, {v, nb, v}), lad_build);
       }
       {
         Scope sc(h, "ladder_antisym");
@@ -462,7 +519,9 @@ static void compute_residual(Handle& h) {
     contract(s, "ikcd,kdP->icP", ONE, TAU, b.Bov, false, Y);
     contract(s, "icP,acP->ia", ONE, Y, b.Bvv, true, S1);
     contract(s, "klic,klca->ia", HALF, Vooov, TAU, true, S1);
-    contract(s, "aikc,kc->ia", MONE, Vvovo, t1, true, S1);
+    // - sum_kc <ak||ci> t_k^c = - sum_kP Vt^P_ak B^P_ki + sum_P B^P_ai y^P
+    contract(s, "akP,kiP->ia", MONE, Vt, b.Boo, true, S1);
+    contract(s, "aiP,P->ia", ONE, b.Bvo, view(w.y, {X}), true, S1);
   }
 }
 
@@ -562,7 +621,7 @@ static int assemble(Handle& h, double* xt, double* e, double* s1, double* s2, do
   int nb = 0;
   if (np > 0) {
     nb = assemble_t2_blocks(np);
-    k_assemble_t2<R>(w.Znp, w.Zab, w.Zij, w.R_, h.Voovv_p, h.x + 2 * ov, h.eps, o, v, shift,
+    k_assemble_t2<R>(w.Znp, w.Z, w.R_, h.Voovv_p, h.x + 2 * ov, h.eps, o, v, shift,
                      xt ? xt + 2 * ov : nullptr, e ? e + 2 * ov : nullptr, s2,
                      s2 ? nullptr : h.red + 1, nb, h.s);
   }
@@ -668,6 +727,9 @@ static double one_iteration(Handle& h) {
   h.last32 = was32;
   if (!was32) h.fp64_iters++;
   if (was32 && rnorm < h.op.mixed_switch_tol) {
+    ensure_fp64_classes(h);
+    HIPCHECK(hipStreamSynchronize(h.s));
+    timer_collect(h);
     h.phase32 = false;
     h.fp64_iters = 0;
     h.order.clear();
@@ -696,8 +758,9 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
   if (o < 1 || v < 1 || X < 1) raise(EXACC_ERR_INVALID_ARG, "nocc, nvir and naux must be >= 1");
   if (!eps || !B) raise(EXACC_ERR_INVALID_ARG, "null input pointer");
   if ((int64_t)o * o > 65535) raise(EXACC_ERR_INVALID_ARG, "nocc too large (nocc^2 > 65535)");
-  if (op.precision != EXACC_FP64 && op.precision != EXACC_MIXED_FP32)
-    raise(EXACC_ERR_UNSUPPORTED, "precision mode not built (EXACC_FP64, EXACC_MIXED_FP32 are)");
+  if (op.precision != EXACC_FP64 && op.precision != EXACC_MIXED_FP32 &&
+      op.precision != EXACC_MIXED_BF16X3)
+    raise(EXACC_ERR_UNSUPPORTED, "unknown precision mode");
   if (op.diis_size < 0 || op.diis_size > 16) raise(EXACC_ERR_INVALID_ARG, "diis_size must be 0..16");
   if (!(op.tol >= 0) || !std::isfinite(op.level_shift))
     raise(EXACC_ERR_INVALID_ARG, "bad tol or level_shift");
@@ -759,43 +822,6 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
       fb.p = nullptr;
     }
     const int64_t oo = (int64_t)o * o;
-    h->Voooo = h->dalloc(oo * oo);
-    h->Vooov = h->dalloc(oo * o * v);
-    h->Voovv = h->dalloc(P.oovv);
-    h->Voovv_p = h->dalloc(P.Po * P.Pv);
-    h->Vvovo = h->dalloc(P.oovv);
-    h->Vvovv_p = h->dalloc((int64_t)v * o * P.Pv);
-    h->x = h->dalloc(P.L);
-    h->diis = h->dalloc(2 * P.nslots * P.L);
-    h->T2 = h->dalloc(P.oovv);
-    h->TAU = h->dalloc(P.oovv);
-    h->taup = h->dalloc(P.Po * P.Pv);
-    h->Tq = h->dalloc(P.oovv);
-    h->Xp = h->dalloc(P.oovv);
-    h->H4 = h->dalloc(P.oovv);
-    h->R = h->dalloc(P.oovv);
-    h->Zij = h->dalloc(P.oovv);
-    h->Zab = h->dalloc(P.oovv);
-    h->Znp = h->dalloc(P.Po * P.Pv);
-    h->Hac = h->dalloc(P.vv);
-    h->Gac = h->dalloc(P.vv);
-    h->Hki = h->dalloc(oo);
-    h->Gki = h->dalloc(oo);
-    h->M1 = h->dalloc(oo);
-    h->Hkc = h->dalloc((int64_t)o * v);
-    h->S1 = h->dalloc((int64_t)o * v);
-    h->t1w = h->dalloc((int64_t)o * v);
-    h->y = h->dalloc(X);
-    h->Zt = h->dalloc(P.vv * X);
-    h->U = h->dalloc(oo * X);
-    h->Vt = h->dalloc((int64_t)v * o * X);
-    h->Y = h->dalloc((int64_t)o * v * X);
-    h->Cp = h->dalloc(P.Po * v * o);
-    h->Cf = h->dalloc(oo * v * o);
-    h->Af = h->dalloc(oo * oo);
-    h->Ap = h->dalloc(P.Po * P.Po);
-    h->Ta = h->dalloc((int64_t)v * std::max(1, v - 1) * v);
-    h->W = h->dalloc(P.chunk_pairs * std::max<int64_t>(1, P.Pv));
     {
       std::vector<int> rm;
       for (int k = 0; k < o; ++k)
@@ -808,33 +834,68 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
         HIPCHECK(hipMemcpyAsync(h->rowmap_o, rm.data(), rm.size() * sizeof(int), hipMemcpyHostToDevice,
                                 h->s));
     }
+    // ---- stored integral classes, before the work arrays (lower create-time peak)
     {
-      double* tmp = nullptr;
-      HIPCHECK(hipMalloc((void**)&tmp, std::max<int64_t>(1, P.vovv_chunk * o * P.vv) * 16));
-      Free ft{tmp};
-      h->ranges.push_back({tmp, (size_t)std::max<int64_t>(1, P.vovv_chunk * o * P.vv) * 16});
+      Scope sc(*h, "integrals");
       h->use();
-      build_integrals(*h, tmp);
+      h->Voooo = h->dalloc(oo * oo);
+      h->Vooov = h->dalloc(oo * o * v);
+      build_oooo_ooov(*h);
+      h->Voovv_p = h->dalloc(P.Po * P.Pv);
+      h->Voovv = h->dalloc(P.oovv);
+      build_oovv(*h, h->Voovv);
+      if (P.Po > 0) k_pack_last2<double>(h->Voovv_p, h->Voovv, h->rowmap_o, P.Po, v, P.vv, h->s);
+      if (op.precision == EXACC_FP64) {
+        h->Vvovv_p = h->dalloc((int64_t)v * o * P.Pv);
+        build_vovv_packed<double>(*h, h->Vvovv_p);
+      } else {
+        // low-precision phase: FP32 copies only; the FP64 classes are rebuilt at the switch
+        auto mk32 = [&](const double* src64, int64_t celems) {
+          float* p = reinterpret_cast<float*>(h->dalloc((celems + 1) / 2));
+          k_cast(src64, p, 2 * celems, h->s);
+          return p;
+        };
+        h->Bt32 = mk32(h->Bt, nnX);
+        h->Voooo32 = mk32(h->Voooo, oo * oo);
+        h->Vooov32 = mk32(h->Vooov, oo * o * v);
+        h->Voovv32 = mk32(h->Voovv, P.oovv);
+        HIPCHECK(hipStreamSynchronize(h->s));
+        h->dfree(h->Voovv);
+        h->Vvovv_p32 = reinterpret_cast<float*>(h->dalloc(((int64_t)v * o * P.Pv + 1) / 2));
+        build_vovv_packed<float>(*h, h->Vvovv_p32);
+        h->phase32 = true;
+      }
       HIPCHECK(hipStreamSynchronize(h->s));
-      h->ranges.pop_back();
-      h->use();
     }
-    if (op.precision == EXACC_MIXED_FP32) {
-      // FP32 copies of the factors and stored classes for the FP32 phase
-      auto mk32 = [&](const double* src64, int64_t celems) {
-        float* p = reinterpret_cast<float*>(h->dalloc((celems + 1) / 2));
-        k_cast(src64, p, 2 * celems, h->s);
-        return p;
-      };
-      h->Bt32 = mk32(h->Bt, nnX);
-      h->Voooo32 = mk32(h->Voooo, oo * oo);
-      h->Vooov32 = mk32(h->Vooov, oo * o * v);
-      h->Voovv32 = mk32(h->Voovv, P.oovv);
-      h->Vvovo32 = mk32(h->Vvovo, P.oovv);
-      h->Vvovv_p32 = mk32(h->Vvovv_p, (int64_t)v * o * P.Pv);
-      h->phase32 = true;
-      h->use();
-    }
+    // ---- amplitudes, DIIS and work arrays
+    h->x = h->dalloc(P.L);
+    h->diis = h->dalloc(2 * P.nslots * P.L);
+    h->TAU = h->dalloc(P.oovv);
+    h->taup = h->dalloc(P.Po * P.Pv);
+    h->Tq = h->dalloc(P.oovv);
+    h->Xp = h->dalloc(P.oovv);
+    h->H4 = h->dalloc(P.oovv);
+    h->Z = h->dalloc(P.oovv);
+    h->Znp = h->dalloc(P.Po * P.Pv);
+    h->Hac = h->dalloc(P.vv);
+    h->Gac = h->dalloc(P.vv);
+    h->Hki = h->dalloc(oo);
+    h->Gki = h->dalloc(oo);
+    h->M1 = h->dalloc(oo);
+    h->Hkc = h->dalloc((int64_t)o * v);
+    h->S1 = h->dalloc((int64_t)o * v);
+    h->t1w = h->dalloc((int64_t)o * v);
+    h->y = h->dalloc(X);
+    h->U = h->dalloc(oo * X);
+    h->Vt = h->dalloc((int64_t)v * o * X);
+    h->Y = h->dalloc((int64_t)o * v * X);
+    h->Cp = h->dalloc(P.Po * v * o);
+    h->Cf = h->dalloc(oo * v * o);
+    h->Af = h->dalloc(oo * oo);
+    h->Ap = h->dalloc(P.Po * P.Po);
+    h->Ta = h->dalloc((int64_t)v * std::max(1, v - 1) * v);
+    h->W = h->dalloc(P.chunk_pairs * std::max<int64_t>(1, P.Pv));
+    h->use();
     HIPCHECK(hipMemsetAsync(h->x, 0, P.L * 16, h->s));
     HIPCHECK(hipStreamSynchronize(h->s));
     timer_collect(*h);
@@ -952,8 +1013,8 @@ int exacc_ccsd_get_amplitudes(exacc_ccsd_t hh, double* t1, double* t2, int on_de
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (t1) HIPCHECK(hipMemcpyAsync(t1, h.x, (size_t)o * v * 16, k, h.s));
     if (t2) {
-      k_unpack_full(h.x, h.x + 2 * (int64_t)o * v, nullptr, h.T2, o, v, h.s);
-      HIPCHECK(hipMemcpyAsync(t2, h.T2, (size_t)h.P.oovv * 16, k, h.s));
+      k_unpack_full(h.x, h.x + 2 * (int64_t)o * v, nullptr, h.Tq, o, v, h.s);
+      HIPCHECK(hipMemcpyAsync(t2, h.Tq, (size_t)h.P.oovv * 16, k, h.s));
     }
     HIPCHECK(hipStreamSynchronize(h.s));
     return (int)EXACC_OK;
@@ -972,8 +1033,8 @@ int exacc_ccsd_set_amplitudes(exacc_ccsd_t hh, const double* t1, const double* t
     else
       HIPCHECK(hipMemsetAsync(h.x, 0, (size_t)o * v * 16, h.s));
     if (t2) {
-      HIPCHECK(hipMemcpyAsync(h.T2, t2, (size_t)h.P.oovv * 16, k, h.s));
-      k_pack_amplitudes(nullptr, h.T2, h.x + 2 * (int64_t)o * v, o, v, h.s);
+      HIPCHECK(hipMemcpyAsync(h.Tq, t2, (size_t)h.P.oovv * 16, k, h.s));
+      k_pack_amplitudes(nullptr, h.Tq, h.x + 2 * (int64_t)o * v, o, v, h.s);
     } else if (h.P.Po * h.P.Pv > 0) {
       HIPCHECK(hipMemsetAsync(h.x + 2 * (int64_t)o * v, 0, (size_t)h.P.Po * h.P.Pv * 16, h.s));
     }

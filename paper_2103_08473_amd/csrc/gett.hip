@@ -417,11 +417,236 @@ static void launch_cfg(const Gett<R>& g, hipStream_t s) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// BF16x3 complex GETT for operands that are K-contiguous FP32 complex (the
+// particle-ladder tile build and contraction in the BF16x3 precision mode).
+// Each FP32 value x is split as hi = bf16(x), lo = bf16(x - hi); a product is
+// hi*hi' + hi*lo' + lo*hi' (lo*lo' dropped), accumulated in FP32 by
+// v_mfma_f32_16x16x32_bf16.  The loader splits re, im and re+im of each
+// operand into six bf16 planes in LDS ([plane][row][k], k contiguous: one
+// 16-byte read per lane per fragment); the 3-multiplication complex product
+// then needs 3 x 3 MFMAs per 16x16 output block per k-step of 32.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
+  const __bf16 h = (__bf16)x;                 // round to nearest even
+  const __bf16 l = (__bf16)(x - (float)h);
+  hi = __builtin_bit_cast(unsigned short, h);
+  lo = __builtin_bit_cast(unsigned short, l);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
+  constexpr int BM = 64, BN = 64, BK = 32;
+  constexpr int PK = BK + 8;  // row pitch in bf16 (16-byte aligned rows)
+  // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo, 4 sum_hi, 5 sum_lo
+  __shared__ __attribute__((aligned(16))) unsigned short sA[6][BM][PK];
+  __shared__ __attribute__((aligned(16))) unsigned short sB[6][BN][PK];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  const int tiles_m = (g.M + BM - 1) / BM;
+  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int64_t batch = blockIdx.y;
+  const float* __restrict__ A = g.A + 2 * batch * g.a_b;
+  const float* __restrict__ B = g.B + 2 * batch * g.b_b;
+  const int kb = blockIdx.z * g.kslice;
+  const int ke = (g.K - kb) < g.kslice ? g.K : kb + g.kslice;
+
+  // loader: thread handles k pair (2*(tid%16), +1) of rows tid/16 + 16*q, q < 4
+  const int kp = 2 * (tid % 16);
+  int64_t aoff[4], boff[4];
+  bool aok[4], bok[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int m = m0 + tid / 16 + 16 * q, n = n0 + tid / 16 + 16 * q;
+    aok[q] = m < g.M;
+    bok[q] = n < g.N;
+    aoff[q] = aok[q] ? cmap(m, g.m_in, g.a_mo, g.a_mi) : 0;
+    boff[q] = bok[q] ? cmap(n, g.n_in, g.b_no, g.b_ni) : 0;
+  }
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  f4v ra[4], rb[4];
+  const float sa = g.conj_a ? -1.f : 1.f, sb = g.conj_b ? -1.f : 1.f;
+  auto load = [&](int k0) {
+    const int k = k0 + kp;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // two consecutive complex (k, k+1); K-contiguous operands, k even, K may be odd
+      f4v va = {0.f, 0.f, 0.f, 0.f}, vb = {0.f, 0.f, 0.f, 0.f};
+      if (aok[q]) {
+        if (k + 1 < ke) {
+          va = *reinterpret_cast<const f4v*>(A + 2 * (aoff[q] + k));
+        } else if (k < ke) {
+          va.x = A[2 * (aoff[q] + k)];
+          va.y = A[2 * (aoff[q] + k) + 1];
+        }
+      }
+      if (bok[q]) {
+        if (k + 1 < ke) {
+          vb = *reinterpret_cast<const f4v*>(B + 2 * (boff[q] + k));
+        } else if (k < ke) {
+          vb.x = B[2 * (boff[q] + k)];
+          vb.y = B[2 * (boff[q] + k) + 1];
+        }
+      }
+      ra[q] = va;
+      rb[q] = vb;
+    }
+  };
+  auto put = [&](unsigned short (*s)[BM][PK], int row, f4v v, float sg) {
+    // v = (re0, im0, re1, im1) at k = kp, kp + 1
+    const float re0 = v.x, im0 = sg * v.y, re1 = v.z, im1 = sg * v.w;
+    unsigned short h0, l0, h1, l1;
+    split_bf16(re0, h0, l0);
+    split_bf16(re1, h1, l1);
+    *reinterpret_cast<unsigned int*>(&s[0][row][kp]) = h0 | ((unsigned)h1 << 16);
+    *reinterpret_cast<unsigned int*>(&s[1][row][kp]) = l0 | ((unsigned)l1 << 16);
+    split_bf16(im0, h0, l0);
+    split_bf16(im1, h1, l1);
+    *reinterpret_cast<unsigned int*>(&s[2][row][kp]) = h0 | ((unsigned)h1 << 16);
+    *reinterpret_cast<unsigned int*>(&s[3][row][kp]) = l0 | ((unsigned)l1 << 16);
+    split_bf16(re0 + im0, h0, l0);
+    split_bf16(re1 + im1, h1, l1);
+    *reinterpret_cast<unsigned int*>(&s[4][row][kp]) = h0 | ((unsigned)h1 << 16);
+    *reinterpret_cast<unsigned int*>(&s[5][row][kp]) = l0 | ((unsigned)l1 << 16);
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      put(sA, tid / 16 + 16 * q, ra[q], sa);
+      put(sB, tid / 16 + 16 * q, rb[q], sb);
+    }
+  };
+
+  // acc[p][i][j]: p = 0 re*re, 1 im*im, 2 sum*sum for the 2x2 16x16 blocks of this wave
+  float4_t acc[3][2][2];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[p][i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
+  if (nk > 0) {
+    load(kb);
+    store();
+  }
+  __syncthreads();
+  const int kq = 8 * (lane >> 4);  // this lane's 8 consecutive k in a fragment
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) load(kb + (kt + 1) * BK);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      bf16x8_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = wm * 32 + 16 * i + (lane & 15);
+        ah[i] = *reinterpret_cast<const bf16x8_t*>(&sA[2 * p][r][kq]);
+        al[i] = *reinterpret_cast<const bf16x8_t*>(&sA[2 * p + 1][r][kq]);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int c = wn * 32 + 16 * j + (lane & 15);
+        bh[j] = *reinterpret_cast<const bf16x8_t*>(&sB[2 * p][c][kq]);
+        bl[j] = *reinterpret_cast<const bf16x8_t*>(&sB[2 * p + 1][c][kq]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[p][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[p][i][j], 0, 0, 0);
+          acc[p][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[p][i][j], 0, 0, 0);
+          acc[p][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[p][i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      store();
+      __syncthreads();
+    }
+  }
+
+  // complex result re = T1 - T2, im = T3 - T1 - T2; 16x16 f32 layout: row 4*(lane/16)+r
+  float* __restrict__ Cb = g.C + 2 * batch * g.c_b;
+  float* __restrict__ W = g.ws ? g.ws + 2 * (((int64_t)blockIdx.z * gridDim.y + batch) * g.M) * g.N : nullptr;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn * 32 + 16 * j + (lane & 15);
+      if (col >= g.N) continue;
+      const int64_t co = cmap(col, g.n_in, g.c_no, g.c_ni);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + 16 * i + 4 * (lane >> 4) + r;
+        if (row >= g.M) continue;
+        const float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
+        const float xr = t1 - t2, xi = t3 - t1 - t2;
+        if (gridDim.z > 1) {
+          const int64_t off = 2 * ((int64_t)row * g.N + col);
+          W[off] = xr;
+          W[off + 1] = xi;
+          continue;
+        }
+        const int64_t off = 2 * (co + cmap(row, g.m_in, g.c_mo, g.c_mi));
+        float yr = g.alpha_re * xr - g.alpha_im * xi;
+        float yi = g.alpha_re * xi + g.alpha_im * xr;
+        if (g.accumulate) {
+          yr += Cb[off];
+          yi += Cb[off + 1];
+        }
+        Cb[off] = yr;
+        Cb[off + 1] = yi;
+      }
+    }
+}
+
+template <int KIND>
+static void launch_bf16x3(const Gett<float>& g, hipStream_t s) {
+  const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+  for (int64_t b0 = 0; b0 < g.nbatch; b0 += 65535) {
+    Gett<float> h = g;
+    const int nb = (int)((g.nbatch - b0) < 65535 ? (g.nbatch - b0) : 65535);
+    h.A = g.A + 2 * b0 * g.a_b;
+    h.B = g.B + 2 * b0 * g.b_b;
+    h.C = g.C + 2 * b0 * g.c_b;
+    h.kslice = g.K > 0 ? g.K : 1;
+    h.ws = nullptr;
+    hipLaunchKernelGGL((gett_bf16x3_kernel<KIND>), dim3(tiles, nb, 1), dim3(256), 0, s, h);
+    HIPCHECK(hipGetLastError());
+  }
+}
+
 template <typename R>
-void launch_gett(const Gett<R>& g, int kind, hipStream_t s) {
+void launch_gett(const Gett<R>& g, int kind_in, hipStream_t s) {
+  int kind = kind_in;
   if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return;
   if ((int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) > 0x7fffffffLL)
     raise(-1, "contraction too large for one launch");
+  // BF16x3 kinds: only for FP32 operands that are K-contiguous in both A and B
+  // (16-byte loads of two complex values: even row strides and 16-byte aligned bases)
+  const bool kcontig = g.k_in == g.K && g.a_ki == 1 && g.b_ki == 1 && g.a_mo % 2 == 0 &&
+                       g.a_mi % 2 == 0 && g.b_no % 2 == 0 && g.b_ni % 2 == 0 &&
+                       g.a_b % 2 == 0 && g.b_b % 2 == 0 &&
+                       reinterpret_cast<uintptr_t>(g.A) % 16 == 0 &&
+                       reinterpret_cast<uintptr_t>(g.B) % 16 == 0;
+  if (kind == GETT_LADDER_BUILD_BF16X3 || kind == GETT_LADDER_CONTRACT_BF16X3) {
+    if constexpr (sizeof(R) == sizeof(float)) {
+      if (kcontig) {
+        if (kind == GETT_LADDER_BUILD_BF16X3)
+          launch_bf16x3<GETT_LADDER_BUILD_BF16X3>(g, s);
+        else
+          launch_bf16x3<GETT_LADDER_CONTRACT_BF16X3>(g, s);
+        return;
+      }
+    }
+    kind = (kind == GETT_LADDER_BUILD_BF16X3) ? GETT_LADDER_BUILD : GETT_LADDER_CONTRACT;
+  }
   switch (kind) {
     case GETT_LADDER_BUILD: launch_cfg<R, 64, 64, GETT_LADDER_BUILD>(g, s); break;
     case GETT_LADDER_CONTRACT: launch_cfg<R, 64, 64, GETT_LADDER_CONTRACT>(g, s); break;

@@ -267,6 +267,21 @@ int main() {
   run("icP,acP->ia", ONE, Y, Bvv, true, S1);
   run("klic,klca->ia", HALF, Vooov, TAU, true, S1);
   run("aikc,kc->ia", MONE, Vvovo, t1, true, S1);
+  // T2 read through the permuted ring operand Tq[b][i][k][a]; Z and its i<->j / a<->b swapped views
+  {
+    const int64_t ov = (int64_t)o * v, oov = (int64_t)o * o * v, vv = (int64_t)v * v, ovv = ov * v;
+    auto Tq = mk({v, o, o, v});
+    auto T2v = sview(Tq.p, {o, o, v, v}, {ov, v, 1, oov});
+    auto Zf = mk({o, o, v, v});
+    auto Zji = sview(Zf.p, {o, o, v, v}, {vv, ovv, v, 1});
+    auto Zba = sview(Zf.p, {o, o, v, v}, {ovv, vv, 1, v});
+    run("kj,ikab->ijab", ONE, Gki, T2v, false, Zf);
+    run("kj,ikab->ijab", MONE, Gki, T2v, true, Zji);
+    run("ac,ijcb->ijab", ONE, Gac, T2v, true, Zf);
+    run("ac,ijcb->ijab", MONE, Gac, T2v, true, Zba);
+    run("ijak,kb->ijab", MONE, Cf, t1, true, Zba);
+    run("kc,ikac->ia", ONE, Hkc, T2v, true, S1);
+  }
   // generic: conjugation, complex alpha, batch labels, empty sum
   run("zmk,zkn->zmn", CPX, conj(mk({3, 4, 5})), mk({3, 5, 6}), false, mk({3, 4, 6}));
   run("mk,kn->nm", CPX, mk({7, 2}), conj(mk({2, 9})), true, mk({9, 7}));

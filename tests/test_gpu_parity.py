@@ -214,3 +214,36 @@ def test_mixed_precision_solve_matches_fp64_oracle(lib, o, v, X, seed):
     say("  iterations %d (fp32 %d), |dE| %.2e Eh, max|dT| %.2e" % (len(hist), sum(phases) + 1, dE, dT))
     assert dE <= 1e-7
     assert dT <= 1e-7
+
+
+@pytest.mark.parametrize("o,v,X", [(10, 40, 120), (12, 70, 150), (16, 67, 131)])
+def test_bf16x3_phase_residual(lib, o, v, X):
+    """BF16x3 ladder (and FP32 elsewhere), FP64 assembly: agreement with the FP64 oracle at
+    the split-BF16 level (each product ~2^-16 relative, FP32 sums: 1e-4 of the largest |S|)."""
+    from paper_2103_08473_amd import exacc
+    say("bf16x3 residual case", o, v, X)
+    eps, B = make_system(o, v, X, seed=o * 1000 + v, sigma=0.2)
+    t1, t2 = make_amplitudes(o, v, seed=7 + o, scale=0.1)
+    S1, S2 = residual(eps, build_integrals(B, o), t1, t2)
+    with exacc.CCSD(eps, B, o, precision=exacc.MIXED_BF16X3) as cc:
+        cc.set_amplitudes(t1, t2)
+        g1, g2 = cc.residual()
+    scale = max(np.abs(S2).max(), np.abs(S1).max())
+    e2 = np.abs(g2 - S2).max() / scale
+    e1 = np.abs(g1 - S1).max() / scale
+    say("  rel err S1 %.2e S2 %.2e" % (e1, e2))
+    assert e1 <= 1e-4 and e2 <= 1e-4
+
+
+def test_bf16x3_solve_matches_fp64_oracle(lib):
+    from paper_2103_08473_amd import exacc
+    o, v, X, seed = 6, 40, 120, 2
+    eps, B = make_system(o, v, X, seed=seed)
+    ref = oracle.solve(eps, B, o, max_iter=80, tol=1e-10)
+    with exacc.CCSD(eps, B, o, precision=exacc.MIXED_BF16X3, tol=1e-10, max_iter=80) as cc:
+        e, conv, hist = cc.solve()
+        t1, t2 = cc.amplitudes()
+    dE = abs(e - ref.energy)
+    dT = max(np.abs(t1 - ref.t1).max(), np.abs(t2 - ref.t2).max())
+    say("  bf16x3 solve: iterations %d, |dE| %.2e Eh, max|dT| %.2e" % (len(hist), dE, dT))
+    assert conv and dE <= 1e-7 and dT <= 1e-7
