@@ -141,8 +141,9 @@ def main():
                 "stage_ms_per_iter": {k: round(t / args.steps, 2) for k, t in sm.items()}}
             if prec == exacc.MIXED_FP32:
                 mixed[name]["ladder_build_frac_fp32_peak"] = round(btf / PEAK_FP32_MFMA, 4)
-            else:  # 9 bf16 MFMA products per complex multiply-add = 18 hardware flops
-                mixed[name]["ladder_build_hw_frac_bf16_peak"] = round(btf * 18 / 8 / PEAK_BF16_MFMA, 4)
+            else:  # 4 real products x 3 split terms = 12 bf16 MFMA products (24 flops) per
+                # complex multiply-add, against 8 algorithmic flops
+                mixed[name]["ladder_build_hw_frac_bf16_peak"] = round(btf * 24 / 8 / PEAK_BF16_MFMA, 4)
     del B_d
 
     s_per_iter = dt / args.steps

@@ -57,7 +57,8 @@ enum GettKind {
   GETT_LADDER_CONTRACT = 2,
   GETT_RING = 3,
   GETT_LADDER_BUILD_BF16X3 = 4,     // FP32 operands, BF16x3 products (falls back to FP32 MFMA
-  GETT_LADDER_CONTRACT_BF16X3 = 5   // when an operand is not K-contiguous)
+  GETT_LADDER_CONTRACT_BF16X3 = 5,  // when an operand is not K-contiguous)
+  GETT_RING_BF16X3 = 6
 };
 
 template <typename R>

@@ -368,6 +368,9 @@ static void compute_residual(Handle& h) {
   const int o = h.P.o, v = h.P.v, X = h.P.X;
   const int64_t Po = h.P.Po, Pv = h.P.Pv;
   const hipStream_t s = h.s;
+  // BF16x3 products for the ladder and ring in the low-precision phase of the BF16x3 mode
+  const bool bf = sizeof(R) == sizeof(float) && h.op.precision == EXACC_MIXED_BF16X3;
+  const int ring_kind = bf ? GETT_RING_BF16X3 : GETT_RING;
   Views<R> b = bviews(h, w.Bt);
   const double* t1p = h.x;
   const double* t2p = h.x + 2 * (int64_t)o * v;
@@ -377,7 +380,12 @@ static void compute_residual(Handle& h) {
   auto T2 = sview(w.Tq, {o, o, v, v}, {ov, v, 1, oov});
   auto TAU = view(w.TAU, {o, o, v, v});
   auto taup = view(w.taup, {Po, Pv});
-  auto Voovv = view(w.Voovv, {o, o, v, v});
+  // <kl||cd>: FP64 stored [k][l][c][d]; the FP32 copy is stored [k][c][l][d] so that the
+  // ring build's K = (l, d) is contiguous (BF16x3-eligible); other uses read it strided
+  const int64_t o_vv = (int64_t)o * v * v;
+  auto Voovv = sizeof(R) == sizeof(double)
+                   ? view(w.Voovv, {o, o, v, v})
+                   : sview(w.Voovv, {o, o, v, v}, {o_vv, (int64_t)v, (int64_t)o * v, 1});
   auto Vooov = view(w.Vooov, {o, o, o, v});
   {
     Scope sc(h, "prep");
@@ -422,12 +430,12 @@ static void compute_residual(Handle& h) {
     contract(s, "acP,kiP->aikc", ONE, b.Bvv, U, true, H4);
     contract(s, "aiP,kcP->aikc", MONE, Vt, b.Bov, true, H4);
     contract(s, "klic,la->aikc", MONE, Vooov, t1, true, H4);
-    contract(s, "aild,klcd->aikc", ONE, view(w.Xp, {v, o, o, v}), Voovv, true, H4, GETT_RING);
+    contract(s, "aild,klcd->aikc", ONE, view(w.Xp, {v, o, o, v}), Voovv, true, H4, ring_kind);
   }
   auto Rv = view(w.R_, {o, o, v, v});
   {
     Scope sc(h, "ring");
-    contract(s, "aikc,bjkc->ijab", ONE, H4, view(w.Tq, {v, o, o, v}), false, Rv, GETT_RING);
+    contract(s, "aikc,bjkc->ijab", ONE, H4, view(w.Tq, {v, o, o, v}), false, Rv, ring_kind);
     contract(s, "aiP,bjP->ijab", ONE, Vt, b.Bvo, true, Rv);
   }
   // Z and its views with i<->j or a<->b swapped: a term X launched into Z and,
@@ -474,7 +482,6 @@ static void compute_residual(Handle& h) {
   }
   // particle ladder: Znp[ij][ab] += sum_{c<d} tau[ij][cd] <ab||cd>, <ab||cd> = (ac|bd) - (ad|bc)
   // (BF16x3 products in the low-precision phase of the BF16x3 mode)
-  const bool bf = sizeof(R) == sizeof(float) && h.op.precision == EXACC_MIXED_BF16X3;
   const int lad_build = bf ? GETT_LADDER_BUILD_BF16X3 : GETT_LADDER_BUILD;
   const int lad_contract = bf ? GETT_LADDER_CONTRACT_BF16X3 : GETT_LADDER_CONTRACT;
   if (Po > 0 && Pv > 0) {
@@ -858,7 +865,14 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
         h->Bt32 = mk32(h->Bt, nnX);
         h->Voooo32 = mk32(h->Voooo, oo * oo);
         h->Vooov32 = mk32(h->Vooov, oo * o * v);
-        h->Voovv32 = mk32(h->Voovv, P.oovv);
+        {
+          // [k][c][l][d] layout for the FP32 copy (contiguous (l, d) for the ring build)
+          Views<double> b = bviews(*h, h->Bt);
+          auto Vperm = sview(h->Voovv, {o, o, v, v}, {(int64_t)o * v * v, (int64_t)v, (int64_t)o * v, 1});
+          contract(h->s, "kcP,ldP->klcd", ONE, b.Bov, b.Bov, false, Vperm);
+          contract(h->s, "kdP,lcP->klcd", MONE, b.Bov, b.Bov, true, Vperm);
+          h->Voovv32 = mk32(h->Voovv, P.oovv);
+        }
         HIPCHECK(hipStreamSynchronize(h->s));
         h->dfree(h->Voovv);
         h->Vvovv_p32 = reinterpret_cast<float*>(h->dalloc(((int64_t)v * o * P.Pv + 1) / 2));

@@ -420,13 +420,15 @@ static void launch_cfg(const Gett<R>& g, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // BF16x3 complex GETT for operands that are K-contiguous FP32 complex (the
-// particle-ladder tile build and contraction in the BF16x3 precision mode).
-// Each FP32 value x is split as hi = bf16(x), lo = bf16(x - hi); a product is
-// hi*hi' + hi*lo' + lo*hi' (lo*lo' dropped), accumulated in FP32 by
-// v_mfma_f32_16x16x32_bf16.  The loader splits re, im and re+im of each
-// operand into six bf16 planes in LDS ([plane][row][k], k contiguous: one
-// 16-byte read per lane per fragment); the 3-multiplication complex product
-// then needs 3 x 3 MFMAs per 16x16 output block per k-step of 32.
+// particle-ladder tile build and contraction and the ring contractions in the
+// BF16x3 precision mode).  Each FP32 value x is split as hi = bf16(x),
+// lo = bf16(x - hi); a real product is hi*hi' + hi*lo' + lo*hi' (lo*lo'
+// dropped), accumulated in FP32 by v_mfma_f32_16x16x32_bf16.  The loader splits
+// re and im of each operand into four bf16 planes in LDS ([plane][row][k], k
+// contiguous: one 16-byte read per lane per fragment).  Complex products take
+// the four-multiplication form here (3 x 4 = 12 MFMAs per 16x16 block per
+// k-step of 32): with four planes instead of six the LDS bytes read per MFMA
+// halve, which is what bounds this kernel.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
@@ -437,13 +439,20 @@ __device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned
   lo = __builtin_bit_cast(unsigned short, l);
 }
 
+__device__ __forceinline__ float4_t mma3(bf16x8_t ah, bf16x8_t al, bf16x8_t bh, bf16x8_t bl,
+                                         float4_t c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+}
+
 template <int KIND>
 __global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
   constexpr int BM = 64, BN = 64, BK = 32;
   constexpr int PK = BK + 8;  // row pitch in bf16 (16-byte aligned rows)
-  // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo, 4 sum_hi, 5 sum_lo
-  __shared__ __attribute__((aligned(16))) unsigned short sA[6][BM][PK];
-  __shared__ __attribute__((aligned(16))) unsigned short sB[6][BN][PK];
+  // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
+  __shared__ __attribute__((aligned(16))) unsigned short sA[4][BM][PK];
+  __shared__ __attribute__((aligned(16))) unsigned short sB[4][BN][PK];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -499,20 +508,15 @@ __global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
   };
   auto put = [&](unsigned short (*s)[BM][PK], int row, f4v v, float sg) {
     // v = (re0, im0, re1, im1) at k = kp, kp + 1
-    const float re0 = v.x, im0 = sg * v.y, re1 = v.z, im1 = sg * v.w;
     unsigned short h0, l0, h1, l1;
-    split_bf16(re0, h0, l0);
-    split_bf16(re1, h1, l1);
+    split_bf16(v.x, h0, l0);
+    split_bf16(v.z, h1, l1);
     *reinterpret_cast<unsigned int*>(&s[0][row][kp]) = h0 | ((unsigned)h1 << 16);
     *reinterpret_cast<unsigned int*>(&s[1][row][kp]) = l0 | ((unsigned)l1 << 16);
-    split_bf16(im0, h0, l0);
-    split_bf16(im1, h1, l1);
+    split_bf16(sg * v.y, h0, l0);
+    split_bf16(sg * v.w, h1, l1);
     *reinterpret_cast<unsigned int*>(&s[2][row][kp]) = h0 | ((unsigned)h1 << 16);
     *reinterpret_cast<unsigned int*>(&s[3][row][kp]) = l0 | ((unsigned)l1 << 16);
-    split_bf16(re0 + im0, h0, l0);
-    split_bf16(re1 + im1, h1, l1);
-    *reinterpret_cast<unsigned int*>(&s[4][row][kp]) = h0 | ((unsigned)h1 << 16);
-    *reinterpret_cast<unsigned int*>(&s[5][row][kp]) = l0 | ((unsigned)l1 << 16);
   };
   auto store = [&]() {
 #pragma unroll
@@ -522,14 +526,17 @@ __global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
     }
   };
 
-  // acc[p][i][j]: p = 0 re*re, 1 im*im, 2 sum*sum for the 2x2 16x16 blocks of this wave
-  float4_t acc[3][2][2];
+  // accR = sum re*re - im*im, accI = sum re*im + im*re for the wave's 2x2 16x16 blocks;
+  // -im*im is accumulated as (-im_A) * im_B via a negated-A pass
+  float4_t accR[2][2], accN[2][2], accI[2][2];
 #pragma unroll
-  for (int p = 0; p < 3; ++p)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[p][i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+      accN[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+      accI[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+    }
 
   const int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
   if (nk > 0) {
@@ -540,29 +547,29 @@ __global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
   const int kq = 8 * (lane >> 4);  // this lane's 8 consecutive k in a fragment
   for (int kt = 0; kt < nk; ++kt) {
     if (kt + 1 < nk) load(kb + (kt + 1) * BK);
+    bf16x8_t arh[2], arl[2], aih[2], ail[2];
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      bf16x8_t ah[2], al[2], bh[2], bl[2];
+    for (int i = 0; i < 2; ++i) {
+      const int r = wm * 32 + 16 * i + (lane & 15);
+      arh[i] = *reinterpret_cast<const bf16x8_t*>(&sA[0][r][kq]);
+      arl[i] = *reinterpret_cast<const bf16x8_t*>(&sA[1][r][kq]);
+      aih[i] = *reinterpret_cast<const bf16x8_t*>(&sA[2][r][kq]);
+      ail[i] = *reinterpret_cast<const bf16x8_t*>(&sA[3][r][kq]);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = wn * 32 + 16 * j + (lane & 15);
+      const bf16x8_t brh = *reinterpret_cast<const bf16x8_t*>(&sB[0][c][kq]);
+      const bf16x8_t brl = *reinterpret_cast<const bf16x8_t*>(&sB[1][c][kq]);
+      const bf16x8_t bih = *reinterpret_cast<const bf16x8_t*>(&sB[2][c][kq]);
+      const bf16x8_t bil = *reinterpret_cast<const bf16x8_t*>(&sB[3][c][kq]);
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const int r = wm * 32 + 16 * i + (lane & 15);
-        ah[i] = *reinterpret_cast<const bf16x8_t*>(&sA[2 * p][r][kq]);
-        al[i] = *reinterpret_cast<const bf16x8_t*>(&sA[2 * p + 1][r][kq]);
+        accR[i][j] = mma3(arh[i], arl[i], brh, brl, accR[i][j]);
+        accN[i][j] = mma3(aih[i], ail[i], bih, bil, accN[i][j]);
+        accI[i][j] = mma3(arh[i], arl[i], bih, bil, accI[i][j]);
+        accI[i][j] = mma3(aih[i], ail[i], brh, brl, accI[i][j]);
       }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int c = wn * 32 + 16 * j + (lane & 15);
-        bh[j] = *reinterpret_cast<const bf16x8_t*>(&sB[2 * p][c][kq]);
-        bl[j] = *reinterpret_cast<const bf16x8_t*>(&sB[2 * p + 1][c][kq]);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[p][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[p][i][j], 0, 0, 0);
-          acc[p][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[p][i][j], 0, 0, 0);
-          acc[p][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[p][i][j], 0, 0, 0);
-        }
     }
     __syncthreads();
     if (kt + 1 < nk) {
@@ -571,9 +578,8 @@ __global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
     }
   }
 
-  // complex result re = T1 - T2, im = T3 - T1 - T2; 16x16 f32 layout: row 4*(lane/16)+r
+  // complex result re = accR - accN, im = accI; 16x16 f32 layout: row 4*(lane/16)+r
   float* __restrict__ Cb = g.C + 2 * batch * g.c_b;
-  float* __restrict__ W = g.ws ? g.ws + 2 * (((int64_t)blockIdx.z * gridDim.y + batch) * g.M) * g.N : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -585,14 +591,7 @@ __global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm * 32 + 16 * i + 4 * (lane >> 4) + r;
         if (row >= g.M) continue;
-        const float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
-        const float xr = t1 - t2, xi = t3 - t1 - t2;
-        if (gridDim.z > 1) {
-          const int64_t off = 2 * ((int64_t)row * g.N + col);
-          W[off] = xr;
-          W[off + 1] = xi;
-          continue;
-        }
+        const float xr = accR[i][j][r] - accN[i][j][r], xi = accI[i][j][r];
         const int64_t off = 2 * (co + cmap(row, g.m_in, g.c_mo, g.c_mi));
         float yr = g.alpha_re * xr - g.alpha_im * xi;
         float yi = g.alpha_re * xi + g.alpha_im * xr;
@@ -635,17 +634,22 @@ void launch_gett(const Gett<R>& g, int kind_in, hipStream_t s) {
                        g.a_b % 2 == 0 && g.b_b % 2 == 0 &&
                        reinterpret_cast<uintptr_t>(g.A) % 16 == 0 &&
                        reinterpret_cast<uintptr_t>(g.B) % 16 == 0;
-  if (kind == GETT_LADDER_BUILD_BF16X3 || kind == GETT_LADDER_CONTRACT_BF16X3) {
+  if (kind == GETT_LADDER_BUILD_BF16X3 || kind == GETT_LADDER_CONTRACT_BF16X3 ||
+      kind == GETT_RING_BF16X3) {
     if constexpr (sizeof(R) == sizeof(float)) {
       if (kcontig) {
         if (kind == GETT_LADDER_BUILD_BF16X3)
           launch_bf16x3<GETT_LADDER_BUILD_BF16X3>(g, s);
-        else
+        else if (kind == GETT_LADDER_CONTRACT_BF16X3)
           launch_bf16x3<GETT_LADDER_CONTRACT_BF16X3>(g, s);
+        else
+          launch_bf16x3<GETT_RING_BF16X3>(g, s);
         return;
       }
     }
-    kind = (kind == GETT_LADDER_BUILD_BF16X3) ? GETT_LADDER_BUILD : GETT_LADDER_CONTRACT;
+    kind = (kind == GETT_LADDER_BUILD_BF16X3)     ? GETT_LADDER_BUILD
+           : (kind == GETT_LADDER_CONTRACT_BF16X3) ? GETT_LADDER_CONTRACT
+                                                   : GETT_RING;
   }
   switch (kind) {
     case GETT_LADDER_BUILD: launch_cfg<R, 64, 64, GETT_LADDER_BUILD>(g, s); break;

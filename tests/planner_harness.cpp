@@ -282,6 +282,16 @@ int main() {
     run("ijak,kb->ijab", MONE, Cf, t1, true, Zba);
     run("kc,ikac->ia", ONE, Hkc, T2v, true, S1);
   }
+  // <kl||cd> stored [k][c][l][d] (FP32 copy layout)
+  {
+    auto Vperm = sview(mk({o, v, o, v}).p, {o, o, v, v}, {(int64_t)o * v * v, (int64_t)v, (int64_t)o * v, 1});
+    run("kcP,ldP->klcd", ONE, Bov, Bov, false, Vperm);
+    run("klcd,klda->ac", HALF, Vperm, TAU, false, Hac);
+    run("klcd,licd->ki", HALF, Vperm, TAU, false, Hki);
+    run("klcd,ld->kc", ONE, Vperm, t1, false, Hkc);
+    run("aild,klcd->aikc", ONE, mk({v, o, o, v}), Vperm, true, H4);
+    run("klcd,ijcd->klij", HALF, Vperm, TAU, true, Af);
+  }
   // generic: conjugation, complex alpha, batch labels, empty sum
   run("zmk,zkn->zmn", CPX, conj(mk({3, 4, 5})), mk({3, 5, 6}), false, mk({3, 4, 6}));
   run("mk,kn->nm", CPX, mk({7, 2}), conj(mk({2, 9})), true, mk({9, 7}));
