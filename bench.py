@@ -29,9 +29,43 @@ PEAK_BF16_MFMA = 2516.6  # TFLOP/s, MI355X dense BF16 matrix
 WORKLOAD = dict(nocc=40, nvir=360, naux=1200, seed=0)
 
 
+# HBM bytes per ladder-build launch (mean over the 359 launches of one iteration),
+# from one rocprofv3 pass each of FETCH_SIZE and WRITE_SIZE, scaled by what the
+# counters read for a plain 1 GiB device copy (fetch x2.000, write x1.000).
+# They hold for the FP64 GETT source they were taken with: `gett_source_sha256`
+# hashes gett.hip up to the BF16x3 section, and the figure is reported as null
+# once that text differs.
+TRAFFIC = {"gett_source_sha256": "6b0ff9927cfa02c7d587fc93c5b0083a849a1c7d55604fc9f80fe7d414f807d9",
+           "fetch_bytes": 8.147e9, "write_bytes": 0.377e9}
+GETT_SRC = os.path.join(ROOT, "paper_2103_08473_amd", "csrc", "gett.hip")
+BF16_MARK = "// BF16x3 complex GETT"
+
+
+def gett_fp64_source_sha256():
+    import hashlib
+    with open(GETT_SRC, "rb") as f:
+        text = f.read()
+    cut = text.find(BF16_MARK.encode())
+    return hashlib.sha256(text[:cut] if cut >= 0 else text).hexdigest()
+
+
+def measured_traffic():
+    """Counter-derived HBM bytes per launch, or None if the kernel changed since."""
+    if gett_fp64_source_sha256() != TRAFFIC["gett_source_sha256"]:
+        return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+
+
 def ladder_build_flops(o, v, X):
     Pv = v * (v - 1) / 2
     return 8.0 * 2.0 * X * Pv * Pv
+
+
+def ladder_build_bytes(o, v, X):
+    """Mean algorithmic HBM bytes of one tile-build launch (FP64 complex): read the
+    factor rows of a (v x X) and of all b > a ((v-a-1) v x X), write the v (v-a-1) v tile."""
+    rows_b = (v - 1) / 2.0  # mean of v-a-1 over a = 0..v-2
+    return 16.0 * (v * X + rows_b * v * X + v * rows_b * v)
 
 
 def cpu_baseline(eps, B, o, budget_s=20.0):
@@ -167,7 +201,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "CCSD iteration, complex FP64, nocc=40 nvir=360 naux=1200 seed 0 "
-                               "(size-scaled sigma_B), DIIS(8)",
+                               "(size-scaled sigma_B = 0.00663), DIIS(8)",
                    "nocc": o, "nvir": v, "naux": X, "precision": "fp64"},
         "s_per_iter": round(s_per_iter, 4),
         "ladder_tflops_kernels": round(lad / (ladder_ms * 1e-3) / 1e12, 3),
@@ -177,7 +211,9 @@ def main():
         "stage_ms_per_iter": {k: round(t / args.steps, 2) for k, t in stages.items()},
         "roofline": {"bound": "mfma", "kernel": "ladder tile build (GETT kind 1)",
                      "achieved": round(achieved, 3), "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_MFMA, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_FP64_MFMA, 4), "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch (HBM, counter-derived)",
+                     "algorithmic_bytes_per_launch": ladder_build_bytes(o, v, X),
                      "flops_counted": "8 real flops per complex multiply-add (algorithmic); the "
                                       "kernel's 3-multiplication complex product issues 6",
                      "hw_frac": round(0.75 * achieved / PEAK_FP64_MFMA, 4)},

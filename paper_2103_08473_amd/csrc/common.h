@@ -64,6 +64,16 @@ enum GettKind {
 template <typename R>
 void launch_gett(const Gett<R>& g, int kind, hipStream_t s);
 
+// BF16x3 on pre-split operands (layout in gett.hip): K rounded up to the split
+// width; split `rows` rows of K complex FP32 values (row r at src +
+// (r / group) * group_stride + (r % group) * row_stride complex elements) into
+// dst, 4 * bf16x3_split_k(K) bf16 per row; C[m][n] = sum_k A[m][k] B[n][k].
+int bf16x3_split_k(int K);
+void split_rows_bf16x3(const float* src, int64_t rows, int64_t group, int64_t group_stride,
+                       int64_t row_stride, int K, unsigned short* dst, hipStream_t s);
+void gemm_bf16x3_split(const unsigned short* A, const unsigned short* B, int M, int N, int K, float* C,
+                       int64_t ldc, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // Bandwidth kernels (elementwise.hip).  Sizes in elements; complex arrays are
 // interleaved (re, im).  Packed pair index of (p<q) over m: p*m - p(p+1)/2 + q-p-1.

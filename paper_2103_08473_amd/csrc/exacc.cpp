@@ -93,8 +93,11 @@ static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
                         + B16(p.chunk_pairs * std::max<int64_t>(1, p.Pv))  // W
                         + (256u << 20) + (2u << 20);             // split-K, reductions
   const size_t big64 = B16(p.oovv) + B16((int64_t)v * o * p.Pv);  // Voovv, Vvovv_p (FP64)
+  const size_t bvs = op.precision == EXACC_MIXED_BF16X3
+                        ? B16(p.vv * bf16x3_split_k(X) / 2)       // split B_vv rows, 8 B per k
+                        : 0;
   const size_t big32 = (B16(p.oovv) + B16((int64_t)v * o * p.Pv) + B16(n * n * X) + B16(oo * oo) +
-                        B16(oo * o * v)) / 2;                     // FP32 copies
+                        B16(oo * o * v)) / 2 + bvs;               // FP32 copies
   const size_t vovv_tmp = B16(p.vovv_chunk * vovv_row) + B16(p.vovv_chunk * o * p.Pv);
   const size_t create_peak = B16(n * n * X) * 2 + B16(p.oovv) + big32 + vovv_tmp;  // staging
   const size_t phase64 = common + big64 + vovv_tmp;
@@ -147,6 +150,9 @@ struct Handle {
   // FP32 copies of B and the stored integral classes (mixed precision only)
   float *Bt32 = nullptr, *Voooo32 = nullptr, *Vooov32 = nullptr, *Voovv32 = nullptr,
         *Vvovv_p32 = nullptr;
+  // BF16x3 mode: the virtual-virtual factor rows B[(a,c)][P] split once into
+  // bf16 hi/lo planes (layout of gemm_bf16x3_split), read by every ladder tile build
+  unsigned short* Bvs = nullptr;
   bool phase32 = false;       // current iteration runs its contractions in FP32
   bool last32 = false;        // the last completed iteration ran in FP32
   int fp64_iters = 0;         // FP64 iterations since the last switch
@@ -346,6 +352,7 @@ static void build_vovv_packed(Handle& h, T* dst) {
 static void ensure_fp64_classes(Handle& h) {
   if (h.Voovv && h.Vvovv_p) return;
   Scope sc(h, "switch_to_fp64");
+  h.dfree(h.Bvs);
   h.dfree(h.Bt32);
   h.dfree(h.Voooo32);
   h.dfree(h.Vooov32);
@@ -501,9 +508,15 @@ static void compute_residual(Handle& h) {
       if (rows + nb > h.P.chunk_pairs) flush();
       {
         Scope sc(h, "ladder_build");
-        auto Ba = sview(b.Bvv.p + 2 * (int64_t)a * nX, {v, X}, {X, 1});
-        auto Bb = sview(b.Bvv.p + 2 * (int64_t)(a + 1) * nX, {nb, v, X}, {nX, X, 1});
-        contract(s, "cP,bdP->cbd", ONE, Ba, Bb, false, view(w.Ta, {v, nb, v}), lad_build);
+        if (bf && h.Bvs) {  // Ta[c][b][d] = sum_P B[(a,c)][P] B[(b,d)][P], b > a, pre-split rows
+          const int64_t rs = 4 * (int64_t)bf16x3_split_k(X);
+          gemm_bf16x3_split(h.Bvs + (int64_t)a * v * rs, h.Bvs + (int64_t)(a + 1) * v * rs, v, nb * v,
+                            X, reinterpret_cast<float*>(w.Ta), (int64_t)nb * v, s);
+        } else {
+          auto Ba = sview(b.Bvv.p + 2 * (int64_t)a * nX, {v, X}, {X, 1});
+          auto Bb = sview(b.Bvv.p + 2 * (int64_t)(a + 1) * nX, {nb, v, X}, {nX, X, 1});
+          contract(s, "cP,bdP->cbd", ONE, Ba, Bb, false, view(w.Ta, {v, nb, v}), lad_build);
+        }
       }
       {
         Scope sc(h, "ladder_antisym");
@@ -863,6 +876,12 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
           return p;
         };
         h->Bt32 = mk32(h->Bt, nnX);
+        if (op.precision == EXACC_MIXED_BF16X3 && v > 1) {
+          // rows (a, c) of the vv block: a at stride n*X, c at stride X
+          h->Bvs = reinterpret_cast<unsigned short*>(h->dalloc(P.vv * bf16x3_split_k(X) / 2));
+          split_rows_bf16x3(h->Bt32 + 2 * ((int64_t)o * n + o) * X, P.vv, v, (int64_t)n * X, X, X,
+                            h->Bvs, h->s);
+        }
         h->Voooo32 = mk32(h->Voooo, oo * oo);
         h->Vooov32 = mk32(h->Vooov, oo * o * v);
         {

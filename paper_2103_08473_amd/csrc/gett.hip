@@ -2,14 +2,14 @@
 //
 // One workgroup (4 waves of 64 lanes) owns a BM x BN tile of C; two
 // workgroups per CU (two waves per SIMD) hide LDS and barrier latency.
-// Operand tiles of BK = 16 complex columns are staged through LDS as three
-// real planes, k-major: re, im and re+im, so each 16x16x4 MFMA fragment is
-// read with unit stride.  Complex products use the three-multiplication
+// Operand tiles of BK = 16 complex columns are staged through LDS as two
+// real planes, k-major (re, im), so each 16x16x4 MFMA fragment is read with
+// unit stride; the re+im operand of the Gauss product is formed in registers.  Complex products use the three-multiplication
 // (Gauss) form: T1 = re*re, T2 = im*im, T3 = (re+im)(re+im) accumulate in
 // three MFMA accumulators and C = (T1 - T2) + i (T3 - T1 - T2) at the end,
 // 3 real MFMAs per complex multiply-add instead of 4.  Global loads for the
 // next k-tile are issued into registers before the MFMAs of the current one
-// (single LDS buffer, register prefetch).  Operand addresses come from the composite
+// and written to the second LDS buffer after them (one barrier per k-tile).  Operand addresses come from the composite
 // (outer, inner) index maps of Gett<R>, so permuted and strided tensors are
 // contracted in place without transposes in HBM.
 #include "common.h"
@@ -70,8 +70,9 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
   constexpr int TN = BN / 32;
   typedef typename MF<R>::acc_t acc_t;
 
-  __shared__ R sA[3][BK][LA];  // re, im, re + im
-  __shared__ R sB[3][BK][LB];
+  // [buffer][re, im][k][m]: two buffers, one barrier per k-tile
+  __shared__ R sA[2][2][BK][LA];
+  __shared__ R sB[2][2][BK][LB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -187,41 +188,37 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
     }
   };
 
-  auto store = [&]() {
+  auto store = [&](int buf) {
     if (AKF) {
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
         const int m = tid / BK + 16 * q;
-        sA[0][a_kk][m] = ra[q].x;
-        sA[1][a_kk][m] = sa * ra[q].y;
-        sA[2][a_kk][m] = ra[q].x + sa * ra[q].y;
+        sA[buf][0][a_kk][m] = ra[q].x;
+        sA[buf][1][a_kk][m] = sa * ra[q].y;
       }
     } else {
       constexpr int KS = 256 / BM;
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
         const int k = a_kq + KS * q;
-        sA[0][k][a_mm] = ra[q].x;
-        sA[1][k][a_mm] = sa * ra[q].y;
-        sA[2][k][a_mm] = ra[q].x + sa * ra[q].y;
+        sA[buf][0][k][a_mm] = ra[q].x;
+        sA[buf][1][k][a_mm] = sa * ra[q].y;
       }
     }
     if (BKF) {
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const int n = tid / BK + 16 * q;
-        sB[0][b_kk][n] = rb[q].x;
-        sB[1][b_kk][n] = sb * rb[q].y;
-        sB[2][b_kk][n] = rb[q].x + sb * rb[q].y;
+        sB[buf][0][b_kk][n] = rb[q].x;
+        sB[buf][1][b_kk][n] = sb * rb[q].y;
       }
     } else {
       constexpr int KS = 256 / BN;
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const int k = b_kq + KS * q;
-        sB[0][k][b_nn] = rb[q].x;
-        sB[1][k][b_nn] = sb * rb[q].y;
-        sB[2][k][b_nn] = rb[q].x + sb * rb[q].y;
+        sB[buf][0][k][b_nn] = rb[q].x;
+        sB[buf][1][k][b_nn] = sb * rb[q].y;
       }
     }
   };
@@ -240,10 +237,11 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
   const int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
   if (nk > 0) {
     load(kb);
-    store();
+    store(0);
   }
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
     if (kt + 1 < nk) load(kb + (kt + 1) * BK);
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
@@ -252,16 +250,16 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int m = wm * (BM / 2) + 16 * i + (lane & 15);
-        ar[i] = sA[0][kr][m];
-        ai[i] = sA[1][kr][m];
-        as[i] = sA[2][kr][m];
+        ar[i] = sA[cur][0][kr][m];
+        ai[i] = sA[cur][1][kr][m];
+        as[i] = ar[i] + ai[i];
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int n = wn * (BN / 2) + 16 * j + (lane & 15);
-        br[j] = sB[0][kr][n];
-        bi[j] = sB[1][kr][n];
-        bs[j] = sB[2][kr][n];
+        br[j] = sB[cur][0][kr][n];
+        bi[j] = sB[cur][1][kr][n];
+        bs[j] = br[j] + bi[j];
       }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
@@ -272,11 +270,9 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
           accS[i][j] = MF<R>::mma(as[i], bs[j], accS[i][j]);
         }
     }
+    // the other buffer was last read before the previous barrier
+    if (kt + 1 < nk) store(cur ^ 1);
     __syncthreads();
-    if (kt + 1 < nk) {
-      store();
-      __syncthreads();
-    }
   }
 
   // complex result: re = T1 - T2, im = T3 - T1 - T2
@@ -432,11 +428,16 @@ static void launch_cfg(const Gett<R>& g, hipStream_t s) {
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
-  const __bf16 h = (__bf16)x;                 // round to nearest even
-  const __bf16 l = (__bf16)(x - (float)h);
-  hi = __builtin_bit_cast(unsigned short, h);
-  lo = __builtin_bit_cast(unsigned short, l);
+// Split two FP32 values into packed bf16 pairs: hi = bf16(x) (round to
+// nearest even), lo = bf16(x - hi); element 0 in the low half of each word.
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split_bf16x2(float x0, float x1, unsigned& hi, unsigned& lo) {
+  const f2v_t x = {x0, x1};
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector(x, bf16x2_t));
+  const f2v_t r = {x0 - __builtin_bit_cast(float, hi << 16),
+                   x1 - __builtin_bit_cast(float, hi & 0xffff0000u)};
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf16x2_t));
 }
 
 __device__ __forceinline__ float4_t mma3(bf16x8_t ah, bf16x8_t al, bf16x8_t bh, bf16x8_t bl,
@@ -465,69 +466,72 @@ __global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
   const int kb = blockIdx.z * g.kslice;
   const int ke = (g.K - kb) < g.kslice ? g.K : kb + g.kslice;
 
-  // loader: thread handles k pair (2*(tid%16), +1) of rows tid/16 + 16*q, q < 4
+  // loader: thread handles the k pair (kp, kp + 1), kp = 2*(tid%16), of tile
+  // rows tid/16 + 16*q, q < 4.  Rows past M (columns past N) are clamped to
+  // the last valid one: they feed only output rows (columns) that are never
+  // stored, so their values do not matter, and no load needs a row check.
   const int kp = 2 * (tid % 16);
-  int64_t aoff[4], boff[4];
-  bool aok[4], bok[4];
+  const float* pa[4];
+  const float* pb[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int m = m0 + tid / 16 + 16 * q, n = n0 + tid / 16 + 16 * q;
-    aok[q] = m < g.M;
-    bok[q] = n < g.N;
-    aoff[q] = aok[q] ? cmap(m, g.m_in, g.a_mo, g.a_mi) : 0;
-    boff[q] = bok[q] ? cmap(n, g.n_in, g.b_no, g.b_ni) : 0;
+    int m = m0 + tid / 16 + 16 * q, n = n0 + tid / 16 + 16 * q;
+    m = m < g.M ? m : g.M - 1;
+    n = n < g.N ? n : g.N - 1;
+    pa[q] = A + 2 * (cmap(m, g.m_in, g.a_mo, g.a_mi) + kb + kp);
+    pb[q] = B + 2 * (cmap(n, g.n_in, g.b_no, g.b_ni) + kb + kp);
   }
   typedef float f4v __attribute__((ext_vector_type(4)));
   f4v ra[4], rb[4];
-  const float sa = g.conj_a ? -1.f : 1.f, sb = g.conj_b ? -1.f : 1.f;
-  auto load = [&](int k0) {
-    const int k = k0 + kp;
+  const int klen = ke - kb;
+  auto load = [&](int k0) {  // k0: offset of the tile from kb
+    if (k0 + BK <= klen) {   // whole tile inside the slice
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      // two consecutive complex (k, k+1); K-contiguous operands, k even, K may be odd
-      f4v va = {0.f, 0.f, 0.f, 0.f}, vb = {0.f, 0.f, 0.f, 0.f};
-      if (aok[q]) {
-        if (k + 1 < ke) {
-          va = *reinterpret_cast<const f4v*>(A + 2 * (aoff[q] + k));
-        } else if (k < ke) {
-          va.x = A[2 * (aoff[q] + k)];
-          va.y = A[2 * (aoff[q] + k) + 1];
-        }
+      for (int q = 0; q < 4; ++q) {
+        ra[q] = *reinterpret_cast<const f4v*>(pa[q] + 2 * k0);
+        rb[q] = *reinterpret_cast<const f4v*>(pb[q] + 2 * k0);
       }
-      if (bok[q]) {
-        if (k + 1 < ke) {
-          vb = *reinterpret_cast<const f4v*>(B + 2 * (boff[q] + k));
-        } else if (k < ke) {
-          vb.x = B[2 * (boff[q] + k)];
-          vb.y = B[2 * (boff[q] + k) + 1];
+    } else {  // ragged last tile: K may be odd, k past the slice reads as zero
+      const int k = k0 + kp;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        f4v va = {0.f, 0.f, 0.f, 0.f}, vb = {0.f, 0.f, 0.f, 0.f};
+        if (k + 1 < klen) {
+          va = *reinterpret_cast<const f4v*>(pa[q] + 2 * k0);
+          vb = *reinterpret_cast<const f4v*>(pb[q] + 2 * k0);
+        } else if (k < klen) {
+          va.x = pa[q][2 * k0];
+          va.y = pa[q][2 * k0 + 1];
+          vb.x = pb[q][2 * k0];
+          vb.y = pb[q][2 * k0 + 1];
         }
+        ra[q] = va;
+        rb[q] = vb;
       }
-      ra[q] = va;
-      rb[q] = vb;
     }
   };
-  auto put = [&](unsigned short (*s)[BM][PK], int row, f4v v, float sg) {
+  // sign bits that conjugate an operand (negate both bf16 halves of its imaginary planes)
+  const unsigned sga = g.conj_a ? 0x80008000u : 0u, sgb = g.conj_b ? 0x80008000u : 0u;
+  auto put = [&](unsigned short (*s)[BM][PK], int row, f4v v, unsigned sg) {
     // v = (re0, im0, re1, im1) at k = kp, kp + 1
-    unsigned short h0, l0, h1, l1;
-    split_bf16(v.x, h0, l0);
-    split_bf16(v.z, h1, l1);
-    *reinterpret_cast<unsigned int*>(&s[0][row][kp]) = h0 | ((unsigned)h1 << 16);
-    *reinterpret_cast<unsigned int*>(&s[1][row][kp]) = l0 | ((unsigned)l1 << 16);
-    split_bf16(sg * v.y, h0, l0);
-    split_bf16(sg * v.w, h1, l1);
-    *reinterpret_cast<unsigned int*>(&s[2][row][kp]) = h0 | ((unsigned)h1 << 16);
-    *reinterpret_cast<unsigned int*>(&s[3][row][kp]) = l0 | ((unsigned)l1 << 16);
+    unsigned h, l;
+    split_bf16x2(v.x, v.z, h, l);
+    *reinterpret_cast<unsigned*>(&s[0][row][kp]) = h;
+    *reinterpret_cast<unsigned*>(&s[1][row][kp]) = l;
+    split_bf16x2(v.y, v.w, h, l);
+    *reinterpret_cast<unsigned*>(&s[2][row][kp]) = h ^ sg;
+    *reinterpret_cast<unsigned*>(&s[3][row][kp]) = l ^ sg;
   };
   auto store = [&]() {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      put(sA, tid / 16 + 16 * q, ra[q], sa);
-      put(sB, tid / 16 + 16 * q, rb[q], sb);
+      put(sA, tid / 16 + 16 * q, ra[q], sga);
+      put(sB, tid / 16 + 16 * q, rb[q], sgb);
     }
   };
 
-  // accR = sum re*re - im*im, accI = sum re*im + im*re for the wave's 2x2 16x16 blocks;
-  // -im*im is accumulated as (-im_A) * im_B via a negated-A pass
+  // for the wave's 2x2 16x16 blocks: accR = sum re*re', accN = sum im*im',
+  // accI = sum re*im' + im*re'
   float4_t accR[2][2], accN[2][2], accI[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -603,6 +607,191 @@ __global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
         Cb[off + 1] = yi;
       }
     }
+}
+
+// ---------------------------------------------------------------------------
+// BF16x3 GEMM on pre-split operands.  An operand that many launches read (the
+// virtual-virtual density-fitting rows of the particle-ladder tile build) is
+// split once into bf16 planes in HBM, so the GEMM loader copies bytes to LDS
+// and does no conversion.  Split layout of a row r with K complex values:
+// Kp = K rounded up to a multiple of 32 (zero tail); block kb of 8 k values is
+// 32 bf16 at r*4*Kp + 32*kb, planes re_hi, re_lo, im_hi, im_lo of 8 k each.
+// The split is the same one the loader of gett_bf16x3_kernel applies, and the
+// MFMA sequence is the same, so both kernels give bitwise-equal results.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void split_rows_kernel(const float* __restrict__ src, int64_t rows,
+                                                         int64_t group, int64_t group_stride,
+                                                         int64_t row_stride, int K, int Kp,
+                                                         unsigned short* __restrict__ dst) {
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  const int nkb = Kp / 8;
+  const int64_t tot = rows * nkb;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < tot; t += (int64_t)gridDim.x * 256) {
+    const int64_t r = t / nkb;
+    const int kb = (int)(t - r * nkb);
+    const float* p = src + 2 * ((r / group) * group_stride + (r % group) * row_stride);
+    float re[8], im[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * kb + j;
+      re[j] = k < K ? p[2 * k] : 0.f;
+      im[j] = k < K ? p[2 * k + 1] : 0.f;
+    }
+    u4v rh, rl, ih, il;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      unsigned h, l;
+      split_bf16x2(re[2 * j], re[2 * j + 1], h, l);
+      rh[j] = h;
+      rl[j] = l;
+      split_bf16x2(im[2 * j], im[2 * j + 1], h, l);
+      ih[j] = h;
+      il[j] = l;
+    }
+    u4v* q = reinterpret_cast<u4v*>(dst + r * 4 * (int64_t)Kp + 32 * (int64_t)kb);
+    q[0] = rh;
+    q[1] = rl;
+    q[2] = ih;
+    q[3] = il;
+  }
+}
+
+// C[m][n] = sum_k A[m][k] B[n][k] over pre-split rows (row strides 4*Kp bf16),
+// C complex FP32 row-major with leading dimension ldc (complex elements).
+__global__ __launch_bounds__(256, 2) void gett_bf16x3_split_kernel(const unsigned short* __restrict__ A,
+                                                                  const unsigned short* __restrict__ B,
+                                                                  int M, int N, int Kp, float* __restrict__ C,
+                                                                  int64_t ldc) {
+  constexpr int BM = 64, BN = 64, BK = 32;
+  constexpr int CH = 17;  // 16-byte chunks per LDS row: 4 k blocks x 4 planes + 1 pad
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  __shared__ u4v sA[2][BM][CH];
+  __shared__ u4v sB[2][BN][CH];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  const int tiles_m = (M + BM - 1) / BM;
+  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int64_t rs = 4 * (int64_t)Kp;  // bf16 per row
+
+  // loader: chunk tid%16 (k block (tid%16)/4, plane tid%4) of tile rows tid/16 + 16*q;
+  // rows past M (N) are clamped: they feed only outputs that are not stored
+  const int ch = tid % 16;
+  const u4v* pa[4];
+  const u4v* pb[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int m = m0 + tid / 16 + 16 * q, n = n0 + tid / 16 + 16 * q;
+    m = m < M ? m : M - 1;
+    n = n < N ? n : N - 1;
+    pa[q] = reinterpret_cast<const u4v*>(A + m * rs) + ch;
+    pb[q] = reinterpret_cast<const u4v*>(B + n * rs) + ch;
+  }
+  u4v ra[4], rb[4];
+  auto load = [&](int kt) {  // 16 chunks (256 bytes) per row and k tile
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ra[q] = pa[q][16 * kt];
+      rb[q] = pb[q][16 * kt];
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sA[buf][tid / 16 + 16 * q][ch] = ra[q];
+      sB[buf][tid / 16 + 16 * q][ch] = rb[q];
+    }
+  };
+
+  float4_t accR[2][2], accN[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+      accN[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+      accI[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+    }
+
+  const int nk = Kp / BK;
+  if (nk > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  const int kc = 4 * (lane >> 4);  // this lane's k block (8 k values) in a fragment
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load(kt + 1);
+    bf16x8_t arh[2], arl[2], aih[2], ail[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = wm * 32 + 16 * i + (lane & 15);
+      arh[i] = __builtin_bit_cast(bf16x8_t, sA[cur][r][kc + 0]);
+      arl[i] = __builtin_bit_cast(bf16x8_t, sA[cur][r][kc + 1]);
+      aih[i] = __builtin_bit_cast(bf16x8_t, sA[cur][r][kc + 2]);
+      ail[i] = __builtin_bit_cast(bf16x8_t, sA[cur][r][kc + 3]);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = wn * 32 + 16 * j + (lane & 15);
+      const bf16x8_t brh = __builtin_bit_cast(bf16x8_t, sB[cur][c][kc + 0]);
+      const bf16x8_t brl = __builtin_bit_cast(bf16x8_t, sB[cur][c][kc + 1]);
+      const bf16x8_t bih = __builtin_bit_cast(bf16x8_t, sB[cur][c][kc + 2]);
+      const bf16x8_t bil = __builtin_bit_cast(bf16x8_t, sB[cur][c][kc + 3]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        accR[i][j] = mma3(arh[i], arl[i], brh, brl, accR[i][j]);
+        accN[i][j] = mma3(aih[i], ail[i], bih, bil, accN[i][j]);
+        accI[i][j] = mma3(arh[i], arl[i], bih, bil, accI[i][j]);
+        accI[i][j] = mma3(aih[i], ail[i], brh, brl, accI[i][j]);
+      }
+    }
+    // the other buffer was last read before the previous barrier
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn * 32 + 16 * j + (lane & 15);
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + 16 * i + 4 * (lane >> 4) + r;
+        if (row >= M) continue;
+        float* c = C + 2 * ((int64_t)row * ldc + col);
+        c[0] = accR[i][j][r] - accN[i][j][r];
+        c[1] = accI[i][j][r];
+      }
+    }
+}
+
+int bf16x3_split_k(int K) { return (K + 31) / 32 * 32; }
+
+void split_rows_bf16x3(const float* src, int64_t rows, int64_t group, int64_t group_stride,
+                       int64_t row_stride, int K, unsigned short* dst, hipStream_t s) {
+  if (rows <= 0 || K <= 0) return;
+  const int Kp = bf16x3_split_k(K);
+  const int64_t tot = rows * (Kp / 8);
+  int64_t blocks = (tot + 255) / 256;
+  if (blocks > 65535 * 8) blocks = 65535 * 8;
+  hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, rows,
+                     group > 0 ? group : 1, group_stride, row_stride, K, Kp, dst);
+  HIPCHECK(hipGetLastError());
+}
+
+void gemm_bf16x3_split(const unsigned short* A, const unsigned short* B, int M, int N, int K, float* C,
+                       int64_t ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0) return;
+  const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+  if (tiles > 0x7fffffffLL) raise(-1, "contraction too large for one launch");
+  hipLaunchKernelGGL(gett_bf16x3_split_kernel, dim3((unsigned)tiles), dim3(256), 0, s, A, B, M, N,
+                     bf16x3_split_k(K), C, ldc);
+  HIPCHECK(hipGetLastError());
 }
 
 template <int KIND>

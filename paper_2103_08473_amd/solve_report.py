@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--diis", type=int, default=8)
     ap.add_argument("--max-iter", type=int, default=60)
     ap.add_argument("--modes", default="fp64,mixed_fp32,mixed_bf16x3")
+    ap.add_argument("--sigma", type=float, default=None,
+                    help="width of the DF factor entries (default: the generator's size rule)")
     args = ap.parse_args()
     import torch
 
@@ -72,11 +74,12 @@ def main():
 
     o, v, X = args.nocc, args.nvir, args.naux
     log("generating (%d, %d, %d) seed %d" % (o, v, X, args.seed))
-    eps, B = make_system(o, v, X, seed=args.seed)
+    eps, B = make_system(o, v, X, seed=args.seed, sigma=args.sigma)
     eps_d = torch.from_numpy(eps).cuda()
     B_d = torch.from_numpy(B).cuda()
     del B
-    out = {"system": {"nocc": o, "nvir": v, "naux": X, "seed": args.seed, "tol": args.tol,
+    out = {"system": {"nocc": o, "nvir": v, "naux": X, "seed": args.seed, "sigma": args.sigma,
+                      "tol": args.tol,
                       "diis": args.diis}, "modes": {}}
     ref = None
     for mode in args.modes.split(","):

@@ -19,11 +19,14 @@ Draw order (one ``numpy.random.default_rng(seed)`` stream):
      A = Re + i Im,  B[P] = (A + A^H) / 2
 so E|B[P,p,q]|^2 = sigma^2 for every p, q (real diagonal, circular off-diagonal).
 
-``sigma=None`` selects the size-scaled width sigma_B with
-2 * nvir * sqrt(naux) * sigma_B^2 = 2 * 40 * sqrt(120) * 0.05^2, i.e. the
-spread of the particle-particle ladder operator is held at its value for the
-(10, 40, 120) system, where sigma = 0.05 exactly.  Passing ``sigma=0.05``
-gives the literal distribution at every size.
+``sigma=None`` selects the size-scaled width
+sigma_B = min(0.05, sigma_s), sigma_s^2 = 0.05^2 * (40 * sqrt(10 * 120)) / (nvir * sqrt(nocc * naux)),
+and sigma_s equals 0.05 exactly at (nocc, nvir, naux) = (10, 40, 120).  It holds
+nocc * nvir^2 * naux * sigma^4, the size of the coherent one-body dressing
+terms (sums of <kl||cd> tau over nocc^2 nvir or nocc nvir^2 entries) at or
+below its (10, 40, 120) value; the spread of the particle-particle ladder operator,
+~ 2 * nvir * sqrt(2 naux) * sigma^2, then shrinks as 1/sqrt(nocc / 10).
+Passing ``sigma=0.05`` gives the literal distribution at every size.
 """
 from __future__ import annotations
 
@@ -32,13 +35,15 @@ import math
 import numpy as np
 
 SIGMA_LITERAL = 0.05
-_REF_NVIR, _REF_NAUX = 40, 120
+_REF_NOCC, _REF_NVIR, _REF_NAUX = 10, 40, 120
 
 
-def scaled_sigma(nvir: int, naux: int) -> float:
-    """Width that keeps 2*nvir*sqrt(naux)*sigma^2 at its (40, 120, 0.05) value."""
-    s2 = SIGMA_LITERAL ** 2 * (_REF_NVIR * math.sqrt(_REF_NAUX)) / (nvir * math.sqrt(naux))
-    return math.sqrt(s2)
+def scaled_sigma(nocc: int, nvir: int, naux: int) -> float:
+    """The literal 0.05, reduced where it would exceed the width that keeps
+    nocc * nvir^2 * naux * sigma^4 at its (10, 40, 120, 0.05) value."""
+    s2 = SIGMA_LITERAL ** 2 * (_REF_NVIR * math.sqrt(_REF_NOCC * _REF_NAUX)) / (
+        nvir * math.sqrt(nocc * naux))
+    return min(SIGMA_LITERAL, math.sqrt(s2))
 
 
 def make_system(nocc: int, nvir: int, naux: int, seed: int = 0, sigma: float | None = None):
@@ -46,7 +51,7 @@ def make_system(nocc: int, nvir: int, naux: int, seed: int = 0, sigma: float | N
     if nocc < 1 or nvir < 1 or naux < 1:
         raise ValueError("nocc, nvir and naux must be >= 1")
     if sigma is None:
-        sigma = scaled_sigma(nvir, naux)
+        sigma = scaled_sigma(nocc, nvir, naux)
     n = nocc + nvir
     rng = np.random.default_rng(seed)
     eps_occ = rng.uniform(-2.0, -0.5, nocc)
