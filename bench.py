@@ -35,8 +35,8 @@ WORKLOAD = dict(nocc=40, nvir=360, naux=1200, seed=0)
 # They hold for the FP64 GETT source they were taken with: `gett_source_sha256`
 # hashes gett.hip up to the BF16x3 section, and the figure is reported as null
 # once that text differs.
-TRAFFIC = {"gett_source_sha256": "6b0ff9927cfa02c7d587fc93c5b0083a849a1c7d55604fc9f80fe7d414f807d9",
-           "fetch_bytes": 8.147e9, "write_bytes": 0.377e9}
+TRAFFIC = {"gett_source_sha256": "88e0a7576c5c8779ec28b5df8ad2b1f35c8b9944b8432d7bc422226d1cf050bd",
+           "fetch_bytes": 8.136e9, "write_bytes": 0.377e9}
 GETT_SRC = os.path.join(ROOT, "paper_2103_08473_amd", "csrc", "gett.hip")
 BF16_MARK = "// BF16x3 complex GETT"
 

@@ -58,8 +58,10 @@ typedef struct {
   double tol;                /* .TCONVERG, default 1e-9, on ||Delta||_2 over the unique amplitudes */
   double level_shift;        /* .LSHIFT, default 0: added to every virtual energy in the denominators */
   int    fp64_final_iters;   /* mixed precision: at least this many FP64 iterations at the end (default 3) */
-  double mixed_switch_tol;   /* mixed precision: FP64 contractions once ||Delta|| < this (default 1e-5);
-                                the DIIS subspace restarts at the switch.  Converged requires FP64 */
+  double mixed_switch_tol;   /* mixed precision: FP64 contractions once ||Delta|| < this (default 1e-5),
+                                or once 4 low-precision iterations in a row bring no new lowest
+                                ||Delta|| (the low-precision rounding floor); the DIIS subspace
+                                restarts at the switch.  Converged requires FP64 iterations */
   int    inputs_on_device;   /* 0: eps and B passed to create are host pointers; 1: device pointers */
   void*  stream;             /* hipStream_t to enqueue on; NULL: the handle creates its own */
   size_t hbm_budget_bytes;   /* 0 = unlimited; create fails with EXACC_ERR_NOMEM above it */

@@ -156,6 +156,8 @@ struct Handle {
   bool phase32 = false;       // current iteration runs its contractions in FP32
   bool last32 = false;        // the last completed iteration ran in FP32
   int fp64_iters = 0;         // FP64 iterations since the last switch
+  double best32 = -1.0;       // lowest ||Delta|| of the low-precision phase so far
+  int since_best32 = 0;       // low-precision iterations since that lowest value
   double* red = nullptr;      // reduction partials
   double* redout = nullptr;   // reduced values (device)
   double* host = nullptr;     // pinned readback
@@ -742,11 +744,22 @@ static double one_iteration(Handle& h) {
   h.energy = device_energy(h);
   timer_collect(h);
   h.iters++;
-  // precision schedule: FP32 contractions until the step norm falls below the
-  // switch threshold, then FP64 contractions with a fresh DIIS subspace
+  // precision schedule: low-precision contractions until the step norm falls
+  // below the switch threshold or stops improving (no new lowest value for
+  // kStall iterations: the rounding floor of the low-precision residual), then
+  // FP64 contractions with a fresh DIIS subspace
+  constexpr int kStall = 4;
   h.last32 = was32;
   if (!was32) h.fp64_iters++;
-  if (was32 && rnorm < h.op.mixed_switch_tol) {
+  if (was32) {
+    if (h.best32 < 0.0 || rnorm < h.best32) {
+      h.best32 = rnorm;
+      h.since_best32 = 0;
+    } else {
+      h.since_best32++;
+    }
+  }
+  if (was32 && (rnorm < h.op.mixed_switch_tol || h.since_best32 >= kStall)) {
     ensure_fp64_classes(h);
     HIPCHECK(hipStreamSynchronize(h.s));
     timer_collect(h);

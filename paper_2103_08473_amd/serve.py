@@ -72,7 +72,8 @@ def solve_one(req: Request, opts: dict):
 
 
 class Server:
-    def __init__(self, hbm_budget: int, max_active: int, opts: dict):
+    def __init__(self, hbm_budget: int, max_active: int, opts: dict, progress=None):
+        self.progress = progress
         self.budget = hbm_budget
         self.max_active = max_active
         self.opts = dict(opts)
@@ -117,6 +118,9 @@ class Server:
             req.status = getattr(e, "status", exacc.ERR_DEVICE)
         req.finished = self.now()
         req.inputs = None
+        if self.progress:
+            self.progress("done %d (%d, %d, %d) it %d latency %.2fs" % (
+                req.k, req.nocc, req.nvir, req.naux, req.iterations, req.finished - req.arrival))
         with self.lock:
             self.active -= 1
             self.in_use -= req.mem
@@ -140,7 +144,7 @@ def run_stream(requests: list[Request], rate: float, hbm_budget: int, max_active
     # input generation in spawned processes (no fork of a process that may hold the GPU)
     gen = cf.ProcessPoolExecutor(max_workers=producers, mp_context=multiprocessing.get_context("spawn"))
     futs = [gen.submit(_make_inputs, (r.nocc, r.nvir, r.naux, r.seed)) for r in requests]
-    srv = Server(hbm_budget, max_active, opts)
+    srv = Server(hbm_budget, max_active, opts, progress=progress)
     for req, t_arr, fut in zip(requests, arrivals, futs):
         req.inputs = fut.result()                   # inputs exist before the request "arrives"
         delay = t_arr - srv.now()
@@ -149,7 +153,7 @@ def run_stream(requests: list[Request], rate: float, hbm_budget: int, max_active
         req.arrival = srv.now()
         srv.submit(req)
         if progress:
-            progress(req)
+            progress("arrived %d (%d, %d, %d)" % (req.k, req.nocc, req.nvir, req.naux))
     srv.drain(len(requests))
     gen.shutdown()
     return srv
@@ -175,36 +179,45 @@ def report(reqs: list[Request], makespan: float):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--first", type=int, default=0, help="index of the first request of the stream")
+    ap.add_argument("--out", default=None, help="write per-request records (JSON) here")
     ap.add_argument("--rate", type=float, default=2.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--max-active", type=int, default=8)
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "bf16x3"], default="mixed")
     ap.add_argument("--check-alone", type=int, default=4,
-                    help="re-solve this many requests alone and compare energies bitwise")
+                    help="re-solve this many requests (the smallest) alone and compare energies bitwise")
     args = ap.parse_args()
-    prec = exacc.MIXED_FP32 if args.precision == "mixed" else exacc.FP64
+    prec = {"mixed": exacc.MIXED_FP32, "bf16x3": exacc.MIXED_BF16X3, "fp64": exacc.FP64}[args.precision]
     opts = dict(precision=prec, tol=args.tol, max_iter=80)
     reqs = []
-    for k in range(args.requests):
+    for k in range(args.first, args.first + args.requests):
         o, v, X, seed = serving_request(k)
         reqs.append(Request(k, o, v, X, seed))
     t0 = time.perf_counter()
     srv = run_stream(reqs, args.rate, int(args.hbm_budget_gb * (1 << 30)), args.max_active, opts,
-                     progress=lambda r: print("arrived", r.k, r.nocc, r.nvir, r.naux, flush=True))
+                     progress=lambda m: print(m, flush=True))
     makespan = time.perf_counter() - t0
     out = report(srv.done, makespan)
-    out.update({"rate_per_s": args.rate, "max_active": args.max_active,
+    out.update({"first": args.first, "rate_per_s": args.rate, "max_active": args.max_active,
                 "hbm_budget_gb": args.hbm_budget_gb, "precision": args.precision, "tol": args.tol})
     # each result alone vs in the mix
     same = []
-    for r in sorted(srv.done, key=lambda r: r.k)[:args.check_alone]:
+    for r in sorted(srv.done, key=lambda r: (r.nvir, r.k))[:args.check_alone]:
         alone = Request(r.k, r.nocc, r.nvir, r.naux, r.seed)
         alone.inputs = _make_inputs((r.nocc, r.nvir, r.naux, r.seed))
         solve_one(alone, opts)
         same.append({"k": r.k, "bitwise_equal": alone.energy == r.energy,
                      "abs_diff": abs(alone.energy - r.energy)})
     out["alone_vs_mix"] = same
+    if args.out:
+        recs = [{"k": r.k, "nocc": r.nocc, "nvir": r.nvir, "naux": r.naux, "arrival": r.arrival,
+                 "admitted": r.admitted, "finished": r.finished, "iterations": r.iterations,
+                 "converged": r.converged, "energy": [r.energy.real, r.energy.imag]}
+                for r in sorted(srv.done, key=lambda r: r.k)]
+        with open(args.out, "w") as f:
+            json.dump({"summary": out, "requests": recs}, f)
     print(json.dumps(out), flush=True)
 
 
