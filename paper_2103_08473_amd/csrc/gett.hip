@@ -2,16 +2,18 @@
 //
 // One workgroup (4 waves of 64 lanes) owns a BM x BN tile of C; two
 // workgroups per CU (two waves per SIMD) hide LDS and barrier latency.
-// Operand tiles of BK = 16 complex columns are staged through LDS as two
-// real planes, k-major (re, im), so each 16x16x4 MFMA fragment is read with
-// unit stride; the re+im operand of the Gauss product is formed in registers.  Complex products use the three-multiplication
-// (Gauss) form: T1 = re*re, T2 = im*im, T3 = (re+im)(re+im) accumulate in
-// three MFMA accumulators and C = (T1 - T2) + i (T3 - T1 - T2) at the end,
-// 3 real MFMAs per complex multiply-add instead of 4.  Global loads for the
-// next k-tile are issued into registers before the MFMAs of the current one
-// and written to the second LDS buffer after them (one barrier per k-tile).  Operand addresses come from the composite
-// (outer, inner) index maps of Gett<R>, so permuted and strided tensors are
-// contracted in place without transposes in HBM.
+// Operand tiles of BK complex columns (16 in production) are staged through
+// LDS as two real planes, k-major (re, im), so each 16x16x4 MFMA fragment is
+// read with unit stride; the re+im operand of the Gauss product is formed in
+// registers.  Complex products use the three-multiplication (Gauss) form:
+// T1 = re*re, T2 = im*im, T3 = (re+im)(re+im) accumulate in three MFMA
+// accumulators and C = (T1 - T2) + i (T3 - T1 - T2) at the end, 3 real MFMAs
+// per complex multiply-add instead of 4.  Global loads for the next k-tile
+// are issued into registers before the MFMAs of the current one and written
+// to the second LDS buffer after them (one barrier per k-tile).  Operand
+// addresses come from the composite (outer, inner) index maps of Gett<R>, so
+// permuted and strided tensors are contracted in place without transposes in
+// HBM.
 #include "common.h"
 
 namespace exacc {
@@ -59,9 +61,10 @@ __device__ __forceinline__ C2<R> ldc(const R* p, int64_t off) {
   return c;
 }
 
-template <typename R, int BM, int BN, bool AKF, bool BKF, int KIND>
+template <typename R, int BM, int BN, int BK, bool DB, bool AKF, bool BKF, int KIND>
 __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
-  constexpr int BK = 16;
+  constexpr int NBUF = DB ? 2 : 1;  // DB: double-buffered LDS, one barrier per k-tile
+  constexpr int RS = 256 / BK;      // tile rows per loader pass (k-fast operands)
   constexpr int LA = BM + 1;  // odd row pitch: conflict-free k-major stores
   constexpr int LB = BN + 1;
   constexpr int NA = BM * BK / 256;  // complex elements per thread per tile
@@ -71,8 +74,8 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
   typedef typename MF<R>::acc_t acc_t;
 
   // [buffer][re, im][k][m]: two buffers, one barrier per k-tile
-  __shared__ R sA[2][2][BK][LA];
-  __shared__ R sB[2][2][BK][LB];
+  __shared__ R sA[NBUF][2][BK][LA];
+  __shared__ R sB[NBUF][2][BK][LB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -91,56 +94,52 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
   const int kb = blockIdx.z * g.kslice;
   const int ke = (g.K - kb) < g.kslice ? g.K : kb + g.kslice;
 
-  // ---- per-thread loader geometry
+  // ---- per-thread loader geometry.  Rows past M (columns past N) are clamped
+  // to the last valid one: they feed only output rows (columns) that are never
+  // stored, so no load needs a row check.  Only the ragged last k-tile checks k.
   int64_t a_off[AKF ? NA : 1];
-  bool a_ok[AKF ? NA : 1];
   int a_kk = 0, a_mm = 0, a_kq = 0;
   if (AKF) {
     a_kk = tid % BK;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-      const int m = m0 + tid / BK + 16 * q;
-      a_ok[q] = m < g.M;
-      a_off[q] = a_ok[q] ? cmap(m, g.m_in, g.a_mo, g.a_mi) : 0;
+      const int m = min(m0 + tid / BK + RS * q, g.M - 1);
+      a_off[q] = cmap(m, g.m_in, g.a_mo, g.a_mi);
     }
   } else {
     a_mm = tid % BM;
     a_kq = tid / BM;
-    const int m = m0 + a_mm;
-    a_ok[0] = m < g.M;
-    a_off[0] = a_ok[0] ? cmap(m, g.m_in, g.a_mo, g.a_mi) : 0;
+    a_off[0] = cmap(min(m0 + a_mm, g.M - 1), g.m_in, g.a_mo, g.a_mi);
   }
   int64_t b_off[BKF ? NB : 1];
-  bool b_ok[BKF ? NB : 1];
   int b_kk = 0, b_nn = 0, b_kq = 0;
   if (BKF) {
     b_kk = tid % BK;
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      const int n = n0 + tid / BK + 16 * q;
-      b_ok[q] = n < g.N;
-      b_off[q] = b_ok[q] ? cmap(n, g.n_in, g.b_no, g.b_ni) : 0;
+      const int n = min(n0 + tid / BK + RS * q, g.N - 1);
+      b_off[q] = cmap(n, g.n_in, g.b_no, g.b_ni);
     }
   } else {
     b_nn = tid % BN;
     b_kq = tid / BN;
-    const int n = n0 + b_nn;
-    b_ok[0] = n < g.N;
-    b_off[0] = b_ok[0] ? cmap(n, g.n_in, g.b_no, g.b_ni) : 0;
+    b_off[0] = cmap(min(n0 + b_nn, g.N - 1), g.n_in, g.b_no, g.b_ni);
   }
 
   C2<R> ra[NA], rb[NB];
   const R sa = g.conj_a ? R(-1) : R(1);
   const R sb = g.conj_b ? R(-1) : R(1);
 
-  auto load = [&](int k0) {
+  // CHECK: the k-tile may be ragged (k >= ke reads as zero)
+  auto load_t = [&](int k0, auto check) {
+    constexpr bool CHECK = decltype(check)::value;
     if (AKF) {
       const int k = k0 + a_kk;
-      const bool kv = k < ke;
+      const bool kv = !CHECK || k < ke;
       const int64_t ko = kv ? cmap(k, g.k_in, g.a_ko, g.a_ki) : 0;
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
-        if (kv && a_ok[q]) {
+        if (kv) {
           ra[q] = ldc(A, a_off[q] + ko);
         } else {
           ra[q].x = R(0);
@@ -152,7 +151,7 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
         const int k = k0 + a_kq + KS * q;
-        if (k < ke && a_ok[0]) {
+        if (!CHECK || k < ke) {
           ra[q] = ldc(A, a_off[0] + cmap(k, g.k_in, g.a_ko, g.a_ki));
         } else {
           ra[q].x = R(0);
@@ -162,11 +161,11 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
     }
     if (BKF) {
       const int k = k0 + b_kk;
-      const bool kv = k < ke;
+      const bool kv = !CHECK || k < ke;
       const int64_t ko = kv ? cmap(k, g.k_in, g.b_ko, g.b_ki) : 0;
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        if (kv && b_ok[q]) {
+        if (kv) {
           rb[q] = ldc(B, b_off[q] + ko);
         } else {
           rb[q].x = R(0);
@@ -178,7 +177,7 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const int k = k0 + b_kq + KS * q;
-        if (k < ke && b_ok[0]) {
+        if (!CHECK || k < ke) {
           rb[q] = ldc(B, b_off[0] + cmap(k, g.k_in, g.b_ko, g.b_ki));
         } else {
           rb[q].x = R(0);
@@ -187,12 +186,18 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
       }
     }
   };
+  auto load = [&](int k0) {
+    if (k0 + BK <= ke)
+      load_t(k0, std::false_type{});
+    else
+      load_t(k0, std::true_type{});
+  };
 
   auto store = [&](int buf) {
     if (AKF) {
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
-        const int m = tid / BK + 16 * q;
+        const int m = tid / BK + RS * q;
         sA[buf][0][a_kk][m] = ra[q].x;
         sA[buf][1][a_kk][m] = sa * ra[q].y;
       }
@@ -208,7 +213,7 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
     if (BKF) {
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        const int n = tid / BK + 16 * q;
+        const int n = tid / BK + RS * q;
         sB[buf][0][b_kk][n] = rb[q].x;
         sB[buf][1][b_kk][n] = sb * rb[q].y;
       }
@@ -241,7 +246,7 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
   }
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
+    const int cur = DB ? (kt & 1) : 0;
     if (kt + 1 < nk) load(kb + (kt + 1) * BK);
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
@@ -270,9 +275,17 @@ __global__ __launch_bounds__(256, 2) void gett_kernel(Gett<R> g) {
           accS[i][j] = MF<R>::mma(as[i], bs[j], accS[i][j]);
         }
     }
-    // the other buffer was last read before the previous barrier
-    if (kt + 1 < nk) store(cur ^ 1);
-    __syncthreads();
+    if (DB) {
+      // the other buffer was last read before the previous barrier
+      if (kt + 1 < nk) store(cur ^ 1);
+      __syncthreads();
+    } else {
+      __syncthreads();
+      if (kt + 1 < nk) {
+        store(0);
+        __syncthreads();
+      }
+    }
   }
 
   // complex result: re = T1 - T2, im = T3 - T1 - T2
@@ -387,21 +400,25 @@ static void launch_cfg(const Gett<R>& g, hipStream_t s) {
       if (want > 1024) want = 1024;
       if (want >= 2) {
         int64_t ks = (g.K + want - 1) / want;
-        ks = (ks + 15) / 16 * 16;
+        ks = (ks + 31) / 32 * 32;  // a multiple of every BK
         nz = (int)((g.K + ks - 1) / ks);
         h.kslice = (int)ks;
         h.ws = (R*)g_ws;
       }
     }
     dim3 grid(tiles, nb, nz), block(256);
+    // FP64: BK = 32, one LDS buffer (two barriers per 96 MFMAs); FP32: BK = 16,
+    // two buffers.  Both fill 65 KB (FP64) / 33 KB (FP32) of LDS per workgroup.
+    constexpr int BK = sizeof(R) == 8 ? 32 : 16;
+    constexpr bool DB = sizeof(R) != 8;
     if (akf && bkf)
-      hipLaunchKernelGGL((gett_kernel<R, BM, BN, true, true, KIND>), grid, block, 0, s, h);
+      hipLaunchKernelGGL((gett_kernel<R, BM, BN, BK, DB, true, true, KIND>), grid, block, 0, s, h);
     else if (akf)
-      hipLaunchKernelGGL((gett_kernel<R, BM, BN, true, false, KIND>), grid, block, 0, s, h);
+      hipLaunchKernelGGL((gett_kernel<R, BM, BN, BK, DB, true, false, KIND>), grid, block, 0, s, h);
     else if (bkf)
-      hipLaunchKernelGGL((gett_kernel<R, BM, BN, false, true, KIND>), grid, block, 0, s, h);
+      hipLaunchKernelGGL((gett_kernel<R, BM, BN, BK, DB, false, true, KIND>), grid, block, 0, s, h);
     else
-      hipLaunchKernelGGL((gett_kernel<R, BM, BN, false, false, KIND>), grid, block, 0, s, h);
+      hipLaunchKernelGGL((gett_kernel<R, BM, BN, BK, DB, false, false, KIND>), grid, block, 0, s, h);
     HIPCHECK(hipGetLastError());
     if (nz > 1) {
       const int64_t tot = (int64_t)g.M * g.N * nb;
@@ -447,18 +464,34 @@ __device__ __forceinline__ float4_t mma3(bf16x8_t ah, bf16x8_t al, bf16x8_t bh, 
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
 }
 
-template <int KIND>
-__global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
-  constexpr int BM = 64, BN = 64, BK = 32;
+// Workgroup index after an optional XCD-aware renumbering: workgroups are
+// handed to the 8 XCDs round-robin by id and each XCD has its own L2, so
+// consecutive ids (the m-tiles that share one n-panel of B) land on different
+// L2s.  The renumbering gives each XCD a contiguous run of logical ids; it is
+// a bijection of [0, n), so only the L2 hit rate depends on it.
+__device__ __forceinline__ int xcd_tile(int id, int n) {
+  const int per = (n + 7) / 8, tall = n % 8 == 0 ? 8 : n % 8;
+  const int x = id % 8, l = id / 8;
+  return x < tall ? x * per + l : tall * per + (x - tall) * (per - 1) + l;
+}
+
+// BM x BN workgroup tile, (BM/32) x (BN/32) waves of 32 x 32 outputs each
+template <int KIND, int BM, int BN, bool XCD>
+__global__ __launch_bounds__(64 * (BM / 32) * (BN / 32), (BM * BN == 64 * 64) ? 2 : 1) void
+gett_bf16x3_kernel(Gett<float> g) {
+  constexpr int BK = 32;
+  constexpr int WM = BM / 32, T = 64 * (BM / 32) * (BN / 32);
+  constexpr int QA = BM * 16 / T, QB = BN * 16 / T, RS = T / 16;
   constexpr int PK = BK + 8;  // row pitch in bf16 (16-byte aligned rows)
   // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
   __shared__ __attribute__((aligned(16))) unsigned short sA[4][BM][PK];
   __shared__ __attribute__((aligned(16))) unsigned short sB[4][BN][PK];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w & 1, wn = w >> 1;
+  const int wm = w % WM, wn = w / WM;
   const int tiles_m = (g.M + BM - 1) / BM;
-  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+  const int tile = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int tm = tile % tiles_m, tn = tile / tiles_m;
   const int m0 = tm * BM, n0 = tn * BN;
   const int64_t batch = blockIdx.y;
   const float* __restrict__ A = g.A + 2 * batch * g.a_b;
@@ -467,67 +500,67 @@ __global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
   const int ke = (g.K - kb) < g.kslice ? g.K : kb + g.kslice;
 
   // loader: thread handles the k pair (kp, kp + 1), kp = 2*(tid%16), of tile
-  // rows tid/16 + 16*q, q < 4.  Rows past M (columns past N) are clamped to
-  // the last valid one: they feed only output rows (columns) that are never
-  // stored, so their values do not matter, and no load needs a row check.
+  // rows tid/16 + RS*q.  Rows past M (columns past N) are clamped to the last
+  // valid one: they feed only output rows (columns) that are never stored, so
+  // their values do not matter, and no load needs a row check.
   const int kp = 2 * (tid % 16);
-  const float* pa[4];
-  const float* pb[4];
+  const float* pa[QA];
+  const float* pb[QB];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int m = m0 + tid / 16 + 16 * q, n = n0 + tid / 16 + 16 * q;
-    m = m < g.M ? m : g.M - 1;
-    n = n < g.N ? n : g.N - 1;
+  for (int q = 0; q < QA; ++q) {
+    const int m = min(m0 + tid / 16 + RS * q, g.M - 1);
     pa[q] = A + 2 * (cmap(m, g.m_in, g.a_mo, g.a_mi) + kb + kp);
+  }
+#pragma unroll
+  for (int q = 0; q < QB; ++q) {
+    const int n = min(n0 + tid / 16 + RS * q, g.N - 1);
     pb[q] = B + 2 * (cmap(n, g.n_in, g.b_no, g.b_ni) + kb + kp);
   }
   typedef float f4v __attribute__((ext_vector_type(4)));
-  f4v ra[4], rb[4];
+  f4v ra[QA], rb[QB];
   const int klen = ke - kb;
+  auto ld = [&](const float* p, int k0) {
+    // two consecutive complex (k, k+1) from k0 + kp; past the slice reads as zero
+    const int k = k0 + kp;
+    f4v v = {0.f, 0.f, 0.f, 0.f};
+    if (k + 1 < klen) {
+      v = *reinterpret_cast<const f4v*>(p + 2 * k0);
+    } else if (k < klen) {
+      v.x = p[2 * k0];
+      v.y = p[2 * k0 + 1];
+    }
+    return v;
+  };
   auto load = [&](int k0) {  // k0: offset of the tile from kb
     if (k0 + BK <= klen) {   // whole tile inside the slice
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ra[q] = *reinterpret_cast<const f4v*>(pa[q] + 2 * k0);
-        rb[q] = *reinterpret_cast<const f4v*>(pb[q] + 2 * k0);
-      }
-    } else {  // ragged last tile: K may be odd, k past the slice reads as zero
-      const int k = k0 + kp;
+      for (int q = 0; q < QA; ++q) ra[q] = *reinterpret_cast<const f4v*>(pa[q] + 2 * k0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        f4v va = {0.f, 0.f, 0.f, 0.f}, vb = {0.f, 0.f, 0.f, 0.f};
-        if (k + 1 < klen) {
-          va = *reinterpret_cast<const f4v*>(pa[q] + 2 * k0);
-          vb = *reinterpret_cast<const f4v*>(pb[q] + 2 * k0);
-        } else if (k < klen) {
-          va.x = pa[q][2 * k0];
-          va.y = pa[q][2 * k0 + 1];
-          vb.x = pb[q][2 * k0];
-          vb.y = pb[q][2 * k0 + 1];
-        }
-        ra[q] = va;
-        rb[q] = vb;
-      }
+      for (int q = 0; q < QB; ++q) rb[q] = *reinterpret_cast<const f4v*>(pb[q] + 2 * k0);
+    } else {  // ragged last tile (K may be odd)
+#pragma unroll
+      for (int q = 0; q < QA; ++q) ra[q] = ld(pa[q], k0);
+#pragma unroll
+      for (int q = 0; q < QB; ++q) rb[q] = ld(pb[q], k0);
     }
   };
   // sign bits that conjugate an operand (negate both bf16 halves of its imaginary planes)
   const unsigned sga = g.conj_a ? 0x80008000u : 0u, sgb = g.conj_b ? 0x80008000u : 0u;
-  auto put = [&](unsigned short (*s)[BM][PK], int row, f4v v, unsigned sg) {
+  auto put = [&](auto& sm, int row, f4v v, unsigned sg) {
     // v = (re0, im0, re1, im1) at k = kp, kp + 1
     unsigned h, l;
     split_bf16x2(v.x, v.z, h, l);
-    *reinterpret_cast<unsigned*>(&s[0][row][kp]) = h;
-    *reinterpret_cast<unsigned*>(&s[1][row][kp]) = l;
+    *reinterpret_cast<unsigned*>(&sm[0][row][kp]) = h;
+    *reinterpret_cast<unsigned*>(&sm[1][row][kp]) = l;
     split_bf16x2(v.y, v.w, h, l);
-    *reinterpret_cast<unsigned*>(&s[2][row][kp]) = h ^ sg;
-    *reinterpret_cast<unsigned*>(&s[3][row][kp]) = l ^ sg;
+    *reinterpret_cast<unsigned*>(&sm[2][row][kp]) = h ^ sg;
+    *reinterpret_cast<unsigned*>(&sm[3][row][kp]) = l ^ sg;
   };
   auto store = [&]() {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      put(sA, tid / 16 + 16 * q, ra[q], sga);
-      put(sB, tid / 16 + 16 * q, rb[q], sgb);
-    }
+    for (int q = 0; q < QA; ++q) put(sA, tid / 16 + RS * q, ra[q], sga);
+#pragma unroll
+    for (int q = 0; q < QB; ++q) put(sB, tid / 16 + RS * q, rb[q], sgb);
   };
 
   // for the wave's 2x2 16x16 blocks: accR = sum re*re', accN = sum im*im',
@@ -544,13 +577,13 @@ __global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
 
   const int nk = ke > kb ? (ke - kb + BK - 1) / BK : 0;
   if (nk > 0) {
-    load(kb);
+    load(0);
     store();
   }
   __syncthreads();
   const int kq = 8 * (lane >> 4);  // this lane's 8 consecutive k in a fragment
   for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) load(kb + (kt + 1) * BK);
+    if (kt + 1 < nk) load((kt + 1) * BK);
     bf16x8_t arh[2], arl[2], aih[2], ail[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -583,6 +616,25 @@ __global__ __launch_bounds__(256, 2) void gett_bf16x3_kernel(Gett<float> g) {
   }
 
   // complex result re = accR - accN, im = accI; 16x16 f32 layout: row 4*(lane/16)+r
+  if (gridDim.z > 1) {  // split-K: raw partial sums, reduced by gett_splitk_reduce
+    float* __restrict__ W = g.ws + 2 * (((int64_t)blockIdx.z * gridDim.y + batch) * g.M) * g.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = n0 + wn * 32 + 16 * j + (lane & 15);
+        if (col >= g.N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * 32 + 16 * i + 4 * (lane >> 4) + r;
+          if (row >= g.M) continue;
+          const int64_t off = 2 * ((int64_t)row * g.N + col);
+          W[off] = accR[i][j][r] - accN[i][j][r];
+          W[off + 1] = accI[i][j][r];
+        }
+      }
+    return;
+  }
   float* __restrict__ Cb = g.C + 2 * batch * g.c_b;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -658,50 +710,50 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const float* __restrict
 
 // C[m][n] = sum_k A[m][k] B[n][k] over pre-split rows (row strides 4*Kp bf16),
 // C complex FP32 row-major with leading dimension ldc (complex elements).
-__global__ __launch_bounds__(256, 2) void gett_bf16x3_split_kernel(const unsigned short* __restrict__ A,
-                                                                  const unsigned short* __restrict__ B,
-                                                                  int M, int N, int Kp, float* __restrict__ C,
-                                                                  int64_t ldc) {
-  constexpr int BM = 64, BN = 64, BK = 32;
+// BM x BN workgroup tile, (BM/32) x (BN/32) waves of 32 x 32 outputs each.
+template <int BM, int BN, bool XCD>
+__global__ __launch_bounds__(64 * (BM / 32) * (BN / 32), (BM * BN == 64 * 64) ? 2 : 1) void
+gett_bf16x3_split_kernel(const unsigned short* __restrict__ A, const unsigned short* __restrict__ B, int M,
+                         int N, int Kp, float* __restrict__ C, int64_t ldc) {
+  constexpr int BK = 32;
+  constexpr int WM = BM / 32, T = 64 * (BM / 32) * (BN / 32);
+  constexpr int QA = BM * 16 / T, QB = BN * 16 / T, RS = T / 16;
   constexpr int CH = 17;  // 16-byte chunks per LDS row: 4 k blocks x 4 planes + 1 pad
   typedef unsigned u4v __attribute__((ext_vector_type(4)));
   __shared__ u4v sA[2][BM][CH];
   __shared__ u4v sB[2][BN][CH];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w & 1, wn = w >> 1;
+  const int wm = w % WM, wn = w / WM;
   const int tiles_m = (M + BM - 1) / BM;
-  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
-  const int m0 = tm * BM, n0 = tn * BN;
+  const int tile = XCD ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int m0 = (tile % tiles_m) * BM, n0 = (tile / tiles_m) * BN;
   const int64_t rs = 4 * (int64_t)Kp;  // bf16 per row
 
-  // loader: chunk tid%16 (k block (tid%16)/4, plane tid%4) of tile rows tid/16 + 16*q;
-  // rows past M (N) are clamped: they feed only outputs that are not stored
+  // loader: chunk tid%16 (k block (tid%16)/4, plane tid%4) of tile rows
+  // tid/16 + RS*q; rows past M (N) are clamped: they feed only outputs that
+  // are not stored
   const int ch = tid % 16;
-  const u4v* pa[4];
-  const u4v* pb[4];
+  const u4v* pa[QA];
+  const u4v* pb[QB];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int m = m0 + tid / 16 + 16 * q, n = n0 + tid / 16 + 16 * q;
-    m = m < M ? m : M - 1;
-    n = n < N ? n : N - 1;
-    pa[q] = reinterpret_cast<const u4v*>(A + m * rs) + ch;
-    pb[q] = reinterpret_cast<const u4v*>(B + n * rs) + ch;
-  }
-  u4v ra[4], rb[4];
+  for (int q = 0; q < QA; ++q)
+    pa[q] = reinterpret_cast<const u4v*>(A + min(m0 + tid / 16 + RS * q, M - 1) * rs) + ch;
+#pragma unroll
+  for (int q = 0; q < QB; ++q)
+    pb[q] = reinterpret_cast<const u4v*>(B + min(n0 + tid / 16 + RS * q, N - 1) * rs) + ch;
+  u4v ra[QA], rb[QB];
   auto load = [&](int kt) {  // 16 chunks (256 bytes) per row and k tile
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ra[q] = pa[q][16 * kt];
-      rb[q] = pb[q][16 * kt];
-    }
+    for (int q = 0; q < QA; ++q) ra[q] = pa[q][16 * kt];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) rb[q] = pb[q][16 * kt];
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      sA[buf][tid / 16 + 16 * q][ch] = ra[q];
-      sB[buf][tid / 16 + 16 * q][ch] = rb[q];
-    }
+    for (int q = 0; q < QA; ++q) sA[buf][tid / 16 + RS * q][ch] = ra[q];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) sB[buf][tid / 16 + RS * q][ch] = rb[q];
   };
 
   float4_t accR[2][2], accN[2][2], accI[2][2];
@@ -787,16 +839,22 @@ void split_rows_bf16x3(const float* src, int64_t rows, int64_t group, int64_t gr
 void gemm_bf16x3_split(const unsigned short* A, const unsigned short* B, int M, int N, int K, float* C,
                        int64_t ldc, hipStream_t s) {
   if (M <= 0 || N <= 0) return;
-  const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+  // 128 x 128 tiles (16 waves, one workgroup per CU) in XCD order: 1.22x the
+  // 64 x 64 tiles in plain order on the ladder tile build, bitwise equal
+  constexpr int BM = 128, BN = 128;
+  const int64_t tiles = (int64_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   if (tiles > 0x7fffffffLL) raise(-1, "contraction too large for one launch");
-  hipLaunchKernelGGL(gett_bf16x3_split_kernel, dim3((unsigned)tiles), dim3(256), 0, s, A, B, M, N,
-                     bf16x3_split_k(K), C, ldc);
+  hipLaunchKernelGGL((gett_bf16x3_split_kernel<BM, BN, true>), dim3((unsigned)tiles),
+                     dim3(64 * (BM / 32) * (BN / 32)), 0, s, A, B, M, N, bf16x3_split_k(K), C, ldc);
   HIPCHECK(hipGetLastError());
 }
 
 template <int KIND>
 static void launch_bf16x3(const Gett<float>& g, hipStream_t s) {
-  const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+  // 128 x 128 tiles in XCD order: 1.37x (contraction) and 1.25x (ring) the
+  // 64 x 64 tiles in plain order, bitwise equal
+  constexpr int BM = 128, BN = 128, BK = 32;
+  const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   for (int64_t b0 = 0; b0 < g.nbatch; b0 += 65535) {
     Gett<float> h = g;
     const int nb = (int)((g.nbatch - b0) < 65535 ? (g.nbatch - b0) : 65535);
@@ -805,8 +863,35 @@ static void launch_bf16x3(const Gett<float>& g, hipStream_t s) {
     h.C = g.C + 2 * b0 * g.c_b;
     h.kslice = g.K > 0 ? g.K : 1;
     h.ws = nullptr;
-    hipLaunchKernelGGL((gett_bf16x3_kernel<KIND>), dim3(tiles, nb, 1), dim3(256), 0, s, h);
+    // split K when the output gives fewer workgroups than CUs (one 16-wave
+    // workgroup per CU): slices of >= 1024 k, a multiple of BK (keeps the
+    // 16-byte alignment of the k-pair loads), fixed-order reduction
+    int nz = 1;
+    const int64_t wgs = (int64_t)tiles * nb;
+    if (g_ws && wgs < 256 && g.K >= 2048) {
+      int64_t want = (256 + wgs - 1) / wgs;
+      want = want < g.K / 1024 ? want : g.K / 1024;
+      const int64_t per = (int64_t)g.M * g.N * nb * 2 * (int64_t)sizeof(float);
+      const int64_t cap = per > 0 ? (int64_t)(g_ws_bytes / per) : 0;
+      if (want > cap) want = cap;
+      if (want >= 2) {
+        int64_t ks = (g.K + want - 1) / want;
+        ks = (ks + BK - 1) / BK * BK;
+        nz = (int)((g.K + ks - 1) / ks);
+        h.kslice = (int)ks;
+        h.ws = (float*)g_ws;
+      }
+    }
+    hipLaunchKernelGGL((gett_bf16x3_kernel<KIND, BM, BN, true>), dim3(tiles, nb, nz),
+                       dim3(64 * (BM / 32) * (BN / 32)), 0, s, h);
     HIPCHECK(hipGetLastError());
+    if (nz > 1) {
+      const int64_t tot = (int64_t)g.M * g.N * nb;
+      int64_t blocks = (tot + 255) / 256;
+      if (blocks > 65535 * 8) blocks = 65535 * 8;
+      hipLaunchKernelGGL(gett_splitk_reduce<float>, dim3((unsigned)blocks), dim3(256), 0, s, h, nz, nb);
+      HIPCHECK(hipGetLastError());
+    }
   }
 }
 

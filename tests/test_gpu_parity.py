@@ -216,10 +216,12 @@ def test_mixed_precision_solve_matches_fp64_oracle(lib, o, v, X, seed):
     assert dT <= 1e-7
 
 
-@pytest.mark.parametrize("o,v,X", [(10, 40, 120), (12, 70, 150), (16, 67, 131)])
+@pytest.mark.parametrize("o,v,X", [(10, 40, 120), (12, 70, 150), (16, 67, 131), (6, 110, 100)])
 def test_bf16x3_phase_residual(lib, o, v, X):
     """BF16x3 ladder (and FP32 elsewhere), FP64 assembly: agreement with the FP64 oracle at
-    the split-BF16 level (each product ~2^-16 relative, FP32 sums: 1e-4 of the largest |S|)."""
+    the split-BF16 level (each product ~2^-16 relative, FP32 sums: 1e-4 of the largest |S|).
+    (6, 110, 100): the ladder contraction has K = P_v = 5995 (odd) over 47 output tiles, so it
+    runs split over 5 K slices with a ragged last tile."""
     from paper_2103_08473_amd import exacc
     say("bf16x3 residual case", o, v, X)
     eps, B = make_system(o, v, X, seed=o * 1000 + v, sigma=0.2)
