@@ -145,6 +145,22 @@ def main():
     E = cc.energy()
     cc.close()
 
+    # CCD (doubles only, the paper's CCDOUBLES): same system, FP64
+    ccd = {}
+    if not args.no_mixed:
+        cd = exacc.CCSD(eps_d, B_d, o, stream=stream.cuda_stream, timing=1, tol=1e-9, doubles_only=1)
+        for _ in range(args.warmup):
+            cd.iterate(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            cd.iterate(1)
+        torch.cuda.synchronize()
+        dtc = (time.perf_counter() - t0) / args.steps
+        cd.close()
+        ccd = {"ccd_fp64": {"s_per_iter": round(dtc, 4),
+                            "ccsd_over_ccd_iteration_time": round((dt / args.steps) / dtc, 3)}}
+
     mixed = {}
     if not args.no_mixed:
         # same system, low-precision phases of the mixed schedules
@@ -218,6 +234,7 @@ def main():
                                       "kernel's 3-multiplication complex product issues 6",
                      "hw_frac": round(0.75 * achieved / PEAK_FP64_MFMA, 4)},
     }
+    out.update(ccd)
     out.update(mixed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(eps, B, o)

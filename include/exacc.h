@@ -67,6 +67,9 @@ typedef struct {
   size_t hbm_budget_bytes;   /* 0 = unlimited; create fails with EXACC_ERR_NOMEM above it */
   long   ladder_chunk_pairs; /* a<b pairs per ladder chunk (scratch size); 0 = automatic */
   int    timing;             /* 1: record per-stage HIP-event times (exacc_ccsd_stage_times) */
+  int    doubles_only;       /* .CCDOUBLES: 1 = CCD (T1 held at zero, no T1 equation and no
+                                t1-dependent contractions; exacc_ccsd_residual returns S1 = 0);
+                                default 0 = CCSD */
 } exacc_ccsd_opts;
 
 /* Fill *o with the defaults listed above. */

@@ -271,11 +271,14 @@ class CCSDResult:
 
 
 def solve(eps, B, nocc, max_iter=30, tol=1e-10, diis_size=8, level_shift=0.0, ints=None,
-          callback=None):
+          callback=None, doubles_only=False):
     """Iterate the CCSD equations from t = 0 (first step = MP2), with Jacobi + DIIS.
 
     Iteration k: S = residual(x_k); e_k = -S/D; push (x_k + e_k, e_k); x_{k+1} =
     DIIS extrapolation (or x_k + e_k); E_k = energy(x_{k+1}); stop when ||e_k|| <= tol.
+
+    doubles_only: CCD (the paper's CCDOUBLES keyword), the same equations with
+    T1 held at zero and no T1 equation (its step is zero).
     """
     eps = np.asarray(eps, dtype=np.float64)
     o = nocc
@@ -293,6 +296,8 @@ def solve(eps, B, nocc, max_iter=30, tol=1e-10, diis_size=8, level_shift=0.0, in
     for it in range(1, max_iter + 1):
         S1, S2 = residual(eps, ints, t1, t2)
         dt1, dt2 = jacobi_step(S1, S2, d1, d2)
+        if doubles_only:
+            dt1 = np.zeros_like(dt1)
         x = to_vector(t1, t2)
         e = to_vector(dt1, dt2)
         rnorm = float(np.linalg.norm(e))

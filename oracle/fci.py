@@ -27,13 +27,21 @@ def _core_h(eps, B, nocc):
     return h
 
 
-def fci_two_electron(eps, B):
-    """Correlation energy of the 2-electron FCI ground state (reference |01>)."""
+def fci_two_electron(eps, B, doubles_only=False):
+    """Correlation energy of the 2-electron FCI ground state (reference |01>).
+
+    doubles_only: CI in the space of the reference and its double excitations
+    |ab> (a, b >= 2) only (CID).  For two electrons CCD is exactly this: T2^2
+    cannot act on the reference, so the CCD doubles equations are the CID
+    eigenproblem in intermediate normalisation.
+    """
     n = eps.size
     h = _core_h(eps, B, 2)
     allp = slice(0, n)
     V = antisym(B, allp, allp, allp, allp)
     dets = [(p, q) for p in range(n) for q in range(p + 1, n)]
+    if doubles_only:
+        dets = [(p, q) for (p, q) in dets if (p, q) == (0, 1) or p >= 2]
     m = len(dets)
     H = np.zeros((m, m), dtype=np.complex128)
     for I, (p, q) in enumerate(dets):

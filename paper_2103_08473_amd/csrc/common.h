@@ -100,7 +100,7 @@ void k_assemble_t2(const T* Znp, const T* Z, const T* R, const double* Voovv_p, 
                    double* s2_full, double* partial, int nblk, hipStream_t s);
 template <typename T>
 void k_assemble_t1(const T* S1, const double* t1, const double* eps, int o, int v, double shift,
-                   double* xt, double* e, double* s1_full, double* partial, hipStream_t s);
+                   bool frozen, double* xt, double* e, double* s1_full, double* partial, hipStream_t s);
 // FP64 -> FP32, round to nearest even, nreal reals
 void k_cast(const double* in, float* out, int64_t nreal, hipStream_t s);
 int assemble_t2_blocks(int64_t npairs);

@@ -311,7 +311,7 @@ __global__ void assemble_t2_kernel(const T* __restrict__ Znp, const T* __restric
 template <typename T>
 __global__ void assemble_t1_kernel(const T* __restrict__ S1, const double* __restrict__ t1,
                                    const double* __restrict__ eps, int o, int v, double shift,
-                                   double* __restrict__ xt, double* __restrict__ e,
+                                   int frozen, double* __restrict__ xt, double* __restrict__ e,
                                    double* __restrict__ s1, double* __restrict__ part) {
   const int64_t tot = (int64_t)o * v;
   double acc = 0.0;
@@ -323,7 +323,8 @@ __global__ void assemble_t1_kernel(const T* __restrict__ S1, const double* __res
     if (s1) {
       st(s1, t, s);
     } else {
-      const z dl = scal(-1.0 / (D + shift), s);
+      // frozen (CCD): no T1 equation, the step is zero and t1 stays as it is (zero)
+      const z dl = frozen ? scal(0.0, s) : scal(-1.0 / (D + shift), s);
       st(e, t, dl);
       st(xt, t, add(tt, dl));
       acc += dl.x * dl.x + dl.y * dl.y;
@@ -556,9 +557,9 @@ void k_assemble_t2(const T* Znp, const T* Z, const T* R, const double* Voovv_p, 
 
 template <typename T>
 void k_assemble_t1(const T* S1, const double* t1, const double* eps, int o, int v, double shift,
-                   double* xt, double* e, double* s1_full, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(assemble_t1_kernel<T>, dim3(1), dim3(TB), 0, s, S1, t1, eps, o, v, shift, xt, e,
-                     s1_full, partial);
+                   bool frozen, double* xt, double* e, double* s1_full, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(assemble_t1_kernel<T>, dim3(1), dim3(TB), 0, s, S1, t1, eps, o, v, shift,
+                     frozen ? 1 : 0, xt, e, s1_full, partial);
   HIPCHECK(hipGetLastError());
 }
 
@@ -621,7 +622,7 @@ void k_pack_amplitudes(const double* t1, const double* t2, double* x, int o, int
   template void k_assemble_t2<T>(const T*, const T*, const T*, const double*, const double*,     \
                                  const double*, int, int, double, double*, double*, double*,     \
                                  double*, int, hipStream_t);                                      \
-  template void k_assemble_t1<T>(const T*, const double*, const double*, int, int, double,       \
+  template void k_assemble_t1<T>(const T*, const double*, const double*, int, int, double, bool, \
                                  double*, double*, double*, double*, hipStream_t);
 EXACC_INST(double)
 EXACC_INST(float)

@@ -291,6 +291,11 @@ static Views<R> bviews(Handle& h, R* Bt) {
 }
 
 template <typename R>
+static void dzero(Handle& h, R* dst, int64_t celems) {
+  if (celems > 0) HIPCHECK(hipMemsetAsync(dst, 0, celems * 2 * sizeof(R), h.s));
+}
+
+template <typename R>
 static void dcopy(Handle& h, R* dst, const R* src, int64_t celems) {
   if (celems > 0)
     HIPCHECK(hipMemcpyAsync(dst, src, celems * 2 * sizeof(R), hipMemcpyDeviceToDevice, h.s));
@@ -380,6 +385,8 @@ static void compute_residual(Handle& h) {
   // BF16x3 products for the ladder and ring in the low-precision phase of the BF16x3 mode
   const bool bf = sizeof(R) == sizeof(float) && h.op.precision == EXACC_MIXED_BF16X3;
   const int ring_kind = bf ? GETT_RING_BF16X3 : GETT_RING;
+  // CCD: t1 is zero, so every contraction with a t1 (or U, Vt, y) factor is skipped
+  const bool ccd = h.op.doubles_only != 0;
   Views<R> b = bviews(h, w.Bt);
   const double* t1p = h.x;
   const double* t2p = h.x + 2 * (int64_t)o * v;
@@ -415,9 +422,12 @@ static void compute_residual(Handle& h) {
     Scope sc(h, "onebody");
     contract(s, "klcd,klda->ac", HALF, Voovv, TAU, false, Hac);
     contract(s, "klcd,licd->ki", HALF, Voovv, TAU, false, Hki);
-    contract(s, "klcd,ld->kc", ONE, Voovv, t1, false, Hkc);
     dcopy(h, w.Gac, w.Hac, (int64_t)v * v);
     dcopy(h, w.Gki, w.Hki, (int64_t)o * o);
+  }
+  if (!ccd) {
+    Scope sc(h, "onebody");
+    contract(s, "klcd,ld->kc", ONE, Voovv, t1, false, Hkc);
     // DF t1 intermediates: y^P = sum_kd B^P_kd t_k^d, U^P_ki = sum_d B^P_kd t_i^d,
     // Vt^P_ai = sum_c B^P_ac t_i^c
     auto y = view(w.y, {X});
@@ -436,16 +446,18 @@ static void compute_residual(Handle& h) {
     // <ak||ci> = (ac|ki) - (ai|kc), formed from the factors each iteration
     contract(s, "acP,kiP->aikc", ONE, b.Bvv, b.Boo, false, H4);
     contract(s, "aiP,kcP->aikc", MONE, b.Bvo, b.Bov, true, H4);
-    contract(s, "acP,kiP->aikc", ONE, b.Bvv, U, true, H4);
-    contract(s, "aiP,kcP->aikc", MONE, Vt, b.Bov, true, H4);
-    contract(s, "klic,la->aikc", MONE, Vooov, t1, true, H4);
+    if (!ccd) {
+      contract(s, "acP,kiP->aikc", ONE, b.Bvv, U, true, H4);
+      contract(s, "aiP,kcP->aikc", MONE, Vt, b.Bov, true, H4);
+      contract(s, "klic,la->aikc", MONE, Vooov, t1, true, H4);
+    }
     contract(s, "aild,klcd->aikc", ONE, view(w.Xp, {v, o, o, v}), Voovv, true, H4, ring_kind);
   }
   auto Rv = view(w.R_, {o, o, v, v});
   {
     Scope sc(h, "ring");
     contract(s, "aikc,bjkc->ijab", ONE, H4, view(w.Tq, {v, o, o, v}), false, Rv, ring_kind);
-    contract(s, "aiP,bjP->ijab", ONE, Vt, b.Bvo, true, Rv);
+    if (!ccd) contract(s, "aiP,bjP->ijab", ONE, Vt, b.Bvo, true, Rv);
   }
   // Z and its views with i<->j or a<->b swapped: a term X launched into Z and,
   // negated, into a swapped view accumulates P^-_ij X (or P^-_ab X) directly
@@ -460,7 +472,7 @@ static void compute_residual(Handle& h) {
     contract(s, "ac,ijcb->ijab", ONE, Gac, T2, true, Z);
     contract(s, "ac,ijcb->ijab", MONE, Gac, T2, true, Zba);
   }
-  {
+  if (!ccd) {  // C^{kb}_{ij} enters only through P_ab sum_k C t_k^a
     Scope sc(h, "cterm");
     auto Cp = view(w.Cp, {Po, v, o});
     contract(s, "bkx,px->pbk", MONE, view(w.Vvovv_p, {v, o, Pv}), taup, false, Cp);
@@ -483,8 +495,10 @@ static void compute_residual(Handle& h) {
     Scope sc(h, "hole_ladder");
     auto Af = view(w.Af, {o, o, o, o});
     dcopy(h, w.Af, w.Voooo, (int64_t)o * o * o * o);
-    contract(s, "klic,jc->klij", ONE, Vooov, t1, true, Af);
-    contract(s, "kljc,ic->klij", MONE, Vooov, t1, true, Af);
+    if (!ccd) {
+      contract(s, "klic,jc->klij", ONE, Vooov, t1, true, Af);
+      contract(s, "kljc,ic->klij", MONE, Vooov, t1, true, Af);
+    }
     contract(s, "klcd,ijcd->klij", HALF, Voovv, TAU, true, Af);
     if (Po > 0) k_pack_last2<R>(w.Ap, w.Af, h.rowmap_o, Po, o, (int64_t)o * o, s);
     contract(s, "qp,qx->px", ONE, view(w.Ap, {Po, Po}), taup, false, Znp);
@@ -528,7 +542,9 @@ static void compute_residual(Handle& h) {
     }
     flush();
   }
-  {
+  if (ccd) {
+    dzero(h, w.S1, (int64_t)o * v);
+  } else {
     Scope sc(h, "singles");
     auto S1 = view(w.S1, {o, v});
     contract(s, "ac,ic->ia", ONE, Hac, t1, false, S1);
@@ -639,7 +655,8 @@ static int assemble(Handle& h, double* xt, double* e, double* s1, double* s2, do
   Work<R> w = work<R>(h);
   const int o = h.P.o, v = h.P.v;
   const int64_t ov = (int64_t)o * v, np = h.P.Po * h.P.Pv;
-  k_assemble_t1<R>(w.S1, h.x, h.eps, o, v, shift, xt, e, s1, s1 ? nullptr : h.red, h.s);
+  k_assemble_t1<R>(w.S1, h.x, h.eps, o, v, shift, h.op.doubles_only != 0, xt, e, s1,
+                   s1 ? nullptr : h.red, h.s);
   int nb = 0;
   if (np > 0) {
     nb = assemble_t2_blocks(np);
@@ -795,6 +812,7 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
       op.precision != EXACC_MIXED_BF16X3)
     raise(EXACC_ERR_UNSUPPORTED, "unknown precision mode");
   if (op.diis_size < 0 || op.diis_size > 16) raise(EXACC_ERR_INVALID_ARG, "diis_size must be 0..16");
+  if (op.doubles_only != 0 && op.doubles_only != 1) raise(EXACC_ERR_INVALID_ARG, "doubles_only must be 0 or 1");
   if (!(op.tol >= 0) || !std::isfinite(op.level_shift))
     raise(EXACC_ERR_INVALID_ARG, "bad tol or level_shift");
   Plan P = make_plan(o, v, X, op);
@@ -988,6 +1006,7 @@ void exacc_ccsd_default_opts(exacc_ccsd_opts* o) {
   o->tol = 1e-9;
   o->level_shift = 0.0;
   o->fp64_final_iters = 3;
+  o->doubles_only = 0;
   o->mixed_switch_tol = 1e-5;
 }
 

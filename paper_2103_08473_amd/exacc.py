@@ -36,6 +36,7 @@ class Opts(ctypes.Structure):
         ("hbm_budget_bytes", ctypes.c_size_t),
         ("ladder_chunk_pairs", ctypes.c_long),
         ("timing", ctypes.c_int),
+        ("doubles_only", ctypes.c_int),
     ]
 
 

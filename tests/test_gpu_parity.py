@@ -74,6 +74,38 @@ def test_two_electron_equals_fci(lib, v, X, seed):
     assert abs(e - e_fci) < 1e-10
 
 
+@pytest.mark.parametrize("o,v,X,seed,sigma,iters", [
+    (10, 40, 120, 0, 0.05, 25),
+    (6, 50, 150, 1, None, 20),
+])
+def test_ccd_iterations_match_oracle(lib, o, v, X, seed, sigma, iters):
+    """CCD (doubles_only): energy after every iteration within 1e-10 Eh of the oracle's CCD,
+    and t1 stays exactly zero."""
+    from paper_2103_08473_amd.exacc import CCSD
+    say("ccd iteration case", o, v, X, seed, sigma)
+    eps, B = make_system(o, v, X, seed=seed, sigma=sigma)
+    ref = oracle.solve(eps, B, o, max_iter=iters, tol=1e-10, doubles_only=True)
+    with CCSD(eps, B, o, tol=1e-10, doubles_only=1) as cc:
+        _, conv, hist = cc.solve(max_iter=iters)
+        t1, t2 = cc.amplitudes()
+    assert len(hist) == len(ref.history)
+    for (it, eg, rg), (_, eo, ro) in zip(hist, ref.history):
+        assert abs(eg - eo) <= 1e-10, (it, eg, eo)
+        assert abs(rg - ro) <= 1e-8 * max(1.0, ro), (it, rg, ro)
+    assert np.abs(t1).max() == 0
+    assert np.abs(t2 - ref.t2).max() <= 1e-10
+
+
+def test_ccd_two_electron_equals_cid(lib):
+    from paper_2103_08473_amd.exacc import CCSD
+    eps, B = make_system(2, 14, 30, seed=1, sigma=0.05)
+    e_cid, _, _ = oracle.fci_two_electron(eps, B, doubles_only=True)
+    with CCSD(eps, B, 2, tol=1e-12, max_iter=80, doubles_only=1) as cc:
+        e, conv, _ = cc.solve()
+    assert conv
+    assert abs(e - e_cid) < 1e-10
+
+
 def test_one_electron_is_exact_at_first_step(lib):
     from paper_2103_08473_amd.exacc import CCSD
     eps, B = make_system(1, 9, 20, seed=4, sigma=0.1)

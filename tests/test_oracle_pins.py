@@ -61,6 +61,38 @@ def test_two_electron_ccsd_equals_fci(v, X, seed, sigma):
             assert abs(cab - tau[0, 1, a, b]) < 1e-8
 
 
+@pytest.mark.parametrize("v,X,seed,sigma", [(8, 20, 0, 0.05), (14, 30, 1, 0.05), (12, 25, 2, 0.08)])
+def test_two_electron_ccd_equals_cid(v, X, seed, sigma):
+    """CCD (T1 = 0) for two electrons is CI over the reference and its doubles."""
+    eps, B = make_system(2, v, X, seed=seed, sigma=sigma)
+    res = oracle.solve(eps, B, 2, max_iter=80, tol=1e-12, doubles_only=True)
+    assert res.converged
+    assert np.abs(res.t1).max() == 0
+    e_cid, vec, dets = oracle.fci_two_electron(eps, B, doubles_only=True)
+    assert abs(res.energy - e_cid) < 1e-10
+    c0 = vec[dets.index((0, 1))]
+    for a in range(v):
+        for b in range(a + 1, v):
+            assert abs(vec[dets.index((2 + a, 2 + b))] / c0 - res.t2[0, 1, a, b]) < 1e-8
+    # the singles matter: CCSD (= FCI) differs from CCD (= CID) here
+    e_fci, _, _ = oracle.fci_two_electron(eps, B)
+    assert abs(e_fci - e_cid) > 1e-8
+
+
+def test_ccd_residual_is_brute_force_projection():
+    """The CCD equations are the CCSD doubles equations at t1 = 0: brute-force check."""
+    o, v, X = 3, 5, 12
+    eps, B = make_system(o, v, X, seed=13, sigma=0.3)
+    _, t2 = make_amplitudes(o, v, seed=14, scale=0.1)
+    t1 = np.zeros((o, v), dtype=np.complex128)
+    _, S2 = residual(eps, build_integrals(B, o), t1, t2)
+    n = o + v
+    V = antisym(B, slice(0, n), slice(0, n), slice(0, n), slice(0, n))
+    _, _, S2b = sq_brute.cc_residual(eps, V, o, t1, t2)
+    assert np.abs(S2b).max() > 0.1
+    np.testing.assert_allclose(S2, S2b, atol=1e-13, rtol=0)
+
+
 def test_one_electron_degenerate_case():
     """nocc = 1: no doubles; canonical spinors make the reference exact (E = FCI = 0)."""
     eps, B = make_system(1, 9, 20, seed=4, sigma=0.1)
