@@ -31,12 +31,14 @@ WORKLOAD = dict(nocc=40, nvir=360, naux=1200, seed=0)
 
 # HBM bytes per ladder-build launch (mean over the 359 launches of one iteration),
 # from one rocprofv3 pass each of FETCH_SIZE and WRITE_SIZE, scaled by what the
-# counters read for a plain 1 GiB device copy (fetch x2.000, write x1.000).
+# counters read for a plain 1 GiB device copy (fetch x2.000, write x1.000), and
+# the kernel's MFMA-busy fraction and clock from a third pass.
 # They hold for the FP64 GETT source they were taken with: `gett_source_sha256`
 # hashes gett.hip up to the BF16x3 section, and the figure is reported as null
 # once that text differs.
-TRAFFIC = {"gett_source_sha256": "88e0a7576c5c8779ec28b5df8ad2b1f35c8b9944b8432d7bc422226d1cf050bd",
-           "fetch_bytes": 8.136e9, "write_bytes": 0.377e9}
+TRAFFIC = {"gett_source_sha256": "8bb8d67aeb59ee0bfa310edb2ecfd55e3877387fe5ad0c7983b8f0d45a1aa591",
+           "fetch_bytes": 8.1345e9, "write_bytes": 0.3770e9,
+           "mfma_busy": 0.716, "clock_ghz": 2.31}
 GETT_SRC = os.path.join(ROOT, "paper_2103_08473_amd", "csrc", "gett.hip")
 BF16_MARK = "// BF16x3 complex GETT"
 
@@ -54,6 +56,15 @@ def measured_traffic():
     if gett_fp64_source_sha256() != TRAFFIC["gett_source_sha256"]:
         return None
     return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+
+
+def measured_mfma_busy():
+    """MFMA-busy fraction of the tile-build kernel from SQ_VALU_MFMA_BUSY_CYCLES over
+    GRBM_GUI_ACTIVE x 1024 SIMDs (a separate rocprofv3 pass), and the clock that
+    GRBM_GUI_ACTIVE implies; None if the kernel changed since."""
+    if gett_fp64_source_sha256() != TRAFFIC["gett_source_sha256"]:
+        return None
+    return {"mfma_busy": TRAFFIC["mfma_busy"], "clock_ghz": TRAFFIC["clock_ghz"]}
 
 
 def ladder_build_flops(o, v, X):
@@ -232,7 +243,8 @@ def main():
                      "algorithmic_bytes_per_launch": ladder_build_bytes(o, v, X),
                      "flops_counted": "8 real flops per complex multiply-add (algorithmic); the "
                                       "kernel's 3-multiplication complex product issues 6",
-                     "hw_frac": round(0.75 * achieved / PEAK_FP64_MFMA, 4)},
+                     "hw_frac": round(0.75 * achieved / PEAK_FP64_MFMA, 4),
+                     "counters": measured_mfma_busy()},
     }
     out.update(ccd)
     out.update(mixed)
