@@ -70,6 +70,8 @@ typedef struct {
   int    doubles_only;       /* .CCDOUBLES: 1 = CCD (T1 held at zero, no T1 equation and no
                                 t1-dependent contractions; exacc_ccsd_residual returns S1 = 0);
                                 default 0 = CCSD */
+  int    cc2;                /* .CC2: 1 = CC2 (T1 equation unchanged; doubles from the T1-dressed
+                                <ab||ij> plus the diagonal Fock term); exclusive with doubles_only */
 } exacc_ccsd_opts;
 
 /* Fill *o with the defaults listed above. */

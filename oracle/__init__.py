@@ -16,11 +16,13 @@ Pins (tests/test_oracle_*.py, all CPU):
   * first-iteration energy == closed-form MP2;
   * integral symmetries, amplitude antisymmetry, orbital-phase invariance,
     real-factor limit, Jacobi and DIIS reaching the same fixed point;
-  * the element-by-element residual (large sizes) == the full residual.
+  * the element-by-element residual (large sizes) == the full residual;
+  * CCD (T1 = 0) for two electrons == CI over the reference and its doubles;
+  * CC2 residuals == their defining second-quantised projections.
 """
 from .integrals import antisym, mulliken  # noqa: F401
 from .ccsd import (  # noqa: F401
-    CCSDResult, DIIS, energy, jacobi_step, mp2_energy_iterative, pack_t2, residual,
-    solve, tau, unpack_t2,
+    CCSDResult, DIIS, cc2_residual, energy, jacobi_step, mp2_energy_iterative, pack_t2,
+    residual, solve, tau, unpack_t2,
 )
 from .fci import fci_two_electron, fci_one_electron  # noqa: F401

@@ -270,8 +270,25 @@ class CCSDResult:
     history: list  # (iteration, energy, residual norm)
 
 
+def cc2_residual(eps, ints, t1, t2):
+    """CC2 residuals (Christiansen, Koch and Joergensen's definition; the paper's App. B
+    working equations are its expansion).
+
+    Singles: the CCSD singles equation, unchanged (<mu1| e^-T H e^T |0> with T = T1 + T2
+    reaches singles only through H + [H, T2] after the T1 transformation).
+    Doubles: <mu2| e^-T1 H e^T1 + [F, T2] |0>, i.e. the CCSD doubles residual evaluated at
+    T2 = 0 (the T1-transformed Hamiltonian's doubles projection) plus the diagonal Fock
+    commutator (e_a + e_b - e_i - e_j) t_ij^ab.
+    """
+    o = t1.shape[0]
+    S1, _ = residual(eps, ints, t1, t2)
+    _, S2 = residual(eps, ints, t1, np.zeros_like(t2))
+    _, d2 = denominators(eps, o)
+    return S1, S2 + d2 * t2
+
+
 def solve(eps, B, nocc, max_iter=30, tol=1e-10, diis_size=8, level_shift=0.0, ints=None,
-          callback=None, doubles_only=False):
+          callback=None, doubles_only=False, cc2=False):
     """Iterate the CCSD equations from t = 0 (first step = MP2), with Jacobi + DIIS.
 
     Iteration k: S = residual(x_k); e_k = -S/D; push (x_k + e_k, e_k); x_{k+1} =
@@ -279,7 +296,11 @@ def solve(eps, B, nocc, max_iter=30, tol=1e-10, diis_size=8, level_shift=0.0, in
 
     doubles_only: CCD (the paper's CCDOUBLES keyword), the same equations with
     T1 held at zero and no T1 equation (its step is zero).
+    cc2: CC2 (the paper's CC2 keyword), the residuals of cc2_residual; the
+    energy expression is the CCSD one.
     """
+    if doubles_only and cc2:
+        raise ValueError("CCD and CC2 are exclusive")
     eps = np.asarray(eps, dtype=np.float64)
     o = nocc
     v = eps.size - o
@@ -294,7 +315,7 @@ def solve(eps, B, nocc, max_iter=30, tol=1e-10, diis_size=8, level_shift=0.0, in
     E = 0j
     it = 0
     for it in range(1, max_iter + 1):
-        S1, S2 = residual(eps, ints, t1, t2)
+        S1, S2 = cc2_residual(eps, ints, t1, t2) if cc2 else residual(eps, ints, t1, t2)
         dt1, dt2 = jacobi_step(S1, S2, d1, d2)
         if doubles_only:
             dt1 = np.zeros_like(dt1)

@@ -101,6 +101,9 @@ void k_assemble_t2(const T* Znp, const T* Z, const T* R, const double* Voovv_p, 
 template <typename T>
 void k_assemble_t1(const T* S1, const double* t1, const double* eps, int o, int v, double shift,
                    bool frozen, double* xt, double* e, double* s1_full, double* partial, hipStream_t s);
+// CC2: Vt[a][i][P] += B^P_ai - Q[a][i][P] (the T1-dressed vo DF factor; Bt is [p][q][P])
+template <typename T>
+void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipStream_t s);
 // FP64 -> FP32, round to nearest even, nreal reals
 void k_cast(const double* in, float* out, int64_t nreal, hipStream_t s);
 int assemble_t2_blocks(int64_t npairs);

@@ -278,11 +278,15 @@ __global__ void assemble_t2_kernel(const T* __restrict__ Znp, const T* __restric
     const int64_t ijba = ((int64_t)i * o + j) * vv + (int64_t)b * v + a;
     const int64_t jiab = ((int64_t)j * o + i) * vv + (int64_t)a * v + b;
     const int64_t jiba = ((int64_t)j * o + i) * vv + (int64_t)b * v + a;
-    z s = add(ld(Znp, t), ld(Z, ijab));
-    s = add(s, add(sub(ld(R, ijab), ld(R, jiab)), sub(ld(R, jiba), ld(R, ijba))));
-    z g = ld(Vp, t);
-    s.x += g.x;
-    s.y -= g.y;
+    // Znp, R and Vp may be null (CC2 doubles: Z holds the whole T1-dressed <ab||ij>)
+    z s = ld(Z, ijab);
+    if (Znp) s = add(s, ld(Znp, t));
+    if (R) s = add(s, add(sub(ld(R, ijab), ld(R, jiab)), sub(ld(R, jiba), ld(R, ijba))));
+    if (Vp) {
+      const z g = ld(Vp, t);
+      s.x += g.x;
+      s.y -= g.y;
+    }
     const z tt = ld(t2p, t);
     const double D = eps[o + a] + eps[o + b] - eps[i] - eps[j];
     s = add(s, scal(D, tt));
@@ -555,6 +559,29 @@ void k_assemble_t2(const T* Znp, const T* Z, const T* R, const double* Voovv_p, 
   HIPCHECK(hipGetLastError());
 }
 
+// T1-dressed virtual-occupied DF factor (CC2 doubles): Vt[a][i][P] holds
+// sum_c B^P_ac t_i^c on entry and B^P_ai + sum_c B^P_ac t_i^c - Q[a][i][P] on exit,
+// with Q^P_ai = sum_k t_k^a (B^P_ki + sum_d B^P_kd t_i^d); Bt is [p][q][P].
+template <typename T>
+__global__ void dress_vo_kernel(T* __restrict__ Vt, const T* __restrict__ Bt, const T* __restrict__ Q,
+                                int o, int v, int n, int X) {
+  const int64_t tot = (int64_t)v * o * X;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int64_t ai = t / X, P = t - ai * X;
+    const int a = (int)(ai / o), i = (int)(ai - (int64_t)a * o);
+    const z b = ld(Bt, ((int64_t)(o + a) * n + i) * X + P);
+    st(Vt, t, add(ld(Vt, t), sub(b, ld(Q, t))));
+  }
+}
+
+template <typename T>
+void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipStream_t s) {
+  const int64_t tot = (int64_t)v * o * X;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(dress_vo_kernel<T>, dim3(nblocks(tot)), dim3(TB), 0, s, Vt, Bt, Q, o, v, n, X);
+  HIPCHECK(hipGetLastError());
+}
+
 template <typename T>
 void k_assemble_t1(const T* S1, const double* t1, const double* eps, int o, int v, double shift,
                    bool frozen, double* xt, double* e, double* s1_full, double* partial, hipStream_t s) {
@@ -623,7 +650,8 @@ void k_pack_amplitudes(const double* t1, const double* t2, double* x, int o, int
                                  const double*, int, int, double, double*, double*, double*,     \
                                  double*, int, hipStream_t);                                      \
   template void k_assemble_t1<T>(const T*, const double*, const double*, int, int, double, bool, \
-                                 double*, double*, double*, double*, hipStream_t);
+                                 double*, double*, double*, double*, hipStream_t);               \
+  template void k_dress_vo<T>(T*, const T*, const T*, int, int, int, int, hipStream_t);
 EXACC_INST(double)
 EXACC_INST(float)
 #undef EXACC_INST

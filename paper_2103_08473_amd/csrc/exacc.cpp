@@ -440,6 +440,40 @@ static void compute_residual(Handle& h) {
     contract(s, "akP,kcP->ac", MONE, Vt, b.Bov, true, Gac);
     contract(s, "klic,lc->ki", MONE, Vooov, t1, true, Gki);
   }
+  // singles residual S1 (CCSD's, also CC2's)
+  auto singles = [&]() {
+    Scope sc(h, "singles");
+    auto S1 = view(w.S1, {o, v});
+    contract(s, "ac,ic->ia", ONE, Hac, t1, false, S1);
+    contract(s, "ki,ka->ia", ONE, Hki, t1, true, S1);
+    contract(s, "kc,ikac->ia", ONE, Hkc, T2, true, S1);
+    auto M1 = view(w.M1, {o, o});
+    contract(s, "kc,ic->ki", ONE, Hkc, t1, false, M1);
+    contract(s, "ki,ka->ia", ONE, M1, t1, true, S1);
+    auto Y = view(w.Y, {o, v, X});
+    contract(s, "ikcd,kdP->icP", ONE, TAU, b.Bov, false, Y);
+    contract(s, "icP,acP->ia", ONE, Y, b.Bvv, true, S1);
+    contract(s, "klic,klca->ia", HALF, Vooov, TAU, true, S1);
+    // - sum_kc <ak||ci> t_k^c = - sum_kP Vt^P_ak B^P_ki + sum_P B^P_ai y^P
+    contract(s, "akP,kiP->ia", MONE, Vt, b.Boo, true, S1);
+    contract(s, "aiP,P->ia", ONE, b.Bvo, view(w.y, {X}), true, S1);
+  };
+  if (h.op.cc2) {
+    // CC2 doubles: <ab||ij> of the T1-transformed Hamiltonian, from the dressed factor
+    // B~^P_ai = B^P_ai + sum_c B^P_ac t_i^c - sum_k t_k^a (B^P_ki + sum_d B^P_kd t_i^d);
+    // the assembly adds (e_a + e_b - e_i - e_j) t_ij^ab and nothing else
+    singles();
+    Scope sc(h, "cc2_doubles");
+    auto Q = view(w.Y, {v, o, X});  // the singles' Y is free again
+    contract(s, "kiP,ka->aiP", ONE, U, t1, false, Q);
+    contract(s, "kiP,ka->aiP", ONE, b.Boo, t1, true, Q);
+    k_dress_vo<R>(w.Vt, w.Bt, w.Y, o, v, h.P.n, X, s);
+    auto Z = view(w.Z, {o, o, v, v});
+    auto Zji = sview(w.Z, {o, o, v, v}, {(int64_t)v * v, (int64_t)o * v * v, v, 1});
+    contract(s, "aiP,bjP->ijab", ONE, Vt, Vt, false, Z);
+    contract(s, "aiP,bjP->ijab", MONE, Vt, Vt, true, Zji);
+    return;
+  }
   auto H4 = view(w.H4, {v, o, o, v});
   {
     Scope sc(h, "ring_build");
@@ -542,25 +576,10 @@ static void compute_residual(Handle& h) {
     }
     flush();
   }
-  if (ccd) {
+  if (ccd)
     dzero(h, w.S1, (int64_t)o * v);
-  } else {
-    Scope sc(h, "singles");
-    auto S1 = view(w.S1, {o, v});
-    contract(s, "ac,ic->ia", ONE, Hac, t1, false, S1);
-    contract(s, "ki,ka->ia", ONE, Hki, t1, true, S1);
-    contract(s, "kc,ikac->ia", ONE, Hkc, T2, true, S1);
-    auto M1 = view(w.M1, {o, o});
-    contract(s, "kc,ic->ki", ONE, Hkc, t1, false, M1);
-    contract(s, "ki,ka->ia", ONE, M1, t1, true, S1);
-    auto Y = view(w.Y, {o, v, X});
-    contract(s, "ikcd,kdP->icP", ONE, TAU, b.Bov, false, Y);
-    contract(s, "icP,acP->ia", ONE, Y, b.Bvv, true, S1);
-    contract(s, "klic,klca->ia", HALF, Vooov, TAU, true, S1);
-    // - sum_kc <ak||ci> t_k^c = - sum_kP Vt^P_ak B^P_ki + sum_P B^P_ai y^P
-    contract(s, "akP,kiP->ia", MONE, Vt, b.Boo, true, S1);
-    contract(s, "aiP,P->ia", ONE, b.Bvo, view(w.y, {X}), true, S1);
-  }
+  else
+    singles();
 }
 
 // ------------------------------------------------------------------ small host linear algebra
@@ -660,7 +679,9 @@ static int assemble(Handle& h, double* xt, double* e, double* s1, double* s2, do
   int nb = 0;
   if (np > 0) {
     nb = assemble_t2_blocks(np);
-    k_assemble_t2<R>(w.Znp, w.Z, w.R_, h.Voovv_p, h.x + 2 * ov, h.eps, o, v, shift,
+    const bool cc2 = h.op.cc2 != 0;
+    k_assemble_t2<R>(cc2 ? nullptr : w.Znp, w.Z, cc2 ? nullptr : w.R_, cc2 ? nullptr : h.Voovv_p,
+                     h.x + 2 * ov, h.eps, o, v, shift,
                      xt ? xt + 2 * ov : nullptr, e ? e + 2 * ov : nullptr, s2,
                      s2 ? nullptr : h.red + 1, nb, h.s);
   }
@@ -813,6 +834,8 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
     raise(EXACC_ERR_UNSUPPORTED, "unknown precision mode");
   if (op.diis_size < 0 || op.diis_size > 16) raise(EXACC_ERR_INVALID_ARG, "diis_size must be 0..16");
   if (op.doubles_only != 0 && op.doubles_only != 1) raise(EXACC_ERR_INVALID_ARG, "doubles_only must be 0 or 1");
+  if (op.cc2 != 0 && op.cc2 != 1) raise(EXACC_ERR_INVALID_ARG, "cc2 must be 0 or 1");
+  if (op.cc2 && op.doubles_only) raise(EXACC_ERR_INVALID_ARG, "cc2 and doubles_only are exclusive");
   if (!(op.tol >= 0) || !std::isfinite(op.level_shift))
     raise(EXACC_ERR_INVALID_ARG, "bad tol or level_shift");
   Plan P = make_plan(o, v, X, op);
@@ -1007,6 +1030,7 @@ void exacc_ccsd_default_opts(exacc_ccsd_opts* o) {
   o->level_shift = 0.0;
   o->fp64_final_iters = 3;
   o->doubles_only = 0;
+  o->cc2 = 0;
   o->mixed_switch_tol = 1e-5;
 }
 

@@ -37,6 +37,7 @@ class Opts(ctypes.Structure):
         ("ladder_chunk_pairs", ctypes.c_long),
         ("timing", ctypes.c_int),
         ("doubles_only", ctypes.c_int),
+        ("cc2", ctypes.c_int),
     ]
 
 

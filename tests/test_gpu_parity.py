@@ -106,6 +106,41 @@ def test_ccd_two_electron_equals_cid(lib):
     assert abs(e - e_cid) < 1e-10
 
 
+@pytest.mark.parametrize("o,v,X", [(3, 4, 9), (10, 40, 120), (16, 67, 131), (1, 9, 20), (4, 1, 6)])
+def test_cc2_residual_matches_oracle(lib, o, v, X):
+    """CC2 residuals (T1-dressed doubles + diagonal Fock term; CCSD singles) at random
+    amplitudes, element by element, FP64: 1e-12 of the largest entry."""
+    from paper_2103_08473_amd.exacc import CCSD
+    say("cc2 residual case", o, v, X)
+    eps, B = make_system(o, v, X, seed=o * 1000 + v + 5, sigma=0.2)
+    t1, t2 = make_amplitudes(o, v, seed=9 + o, scale=0.1)
+    S1, S2 = oracle.cc2_residual(eps, build_integrals(B, o), t1, t2)
+    with CCSD(eps, B, o, cc2=1) as cc:
+        cc.set_amplitudes(t1, t2)
+        g1, g2 = cc.residual()
+    scale = max(np.abs(S2).max() if S2.size else 0.0, np.abs(S1).max(), 1e-300)
+    assert np.abs(g1 - S1).max() <= 1e-12 * scale
+    if S2.size:
+        assert np.abs(g2 - S2).max() <= 1e-12 * scale
+
+
+def test_cc2_iterations_match_oracle(lib):
+    """CC2 solve: energy after every iteration within 1e-10 Eh of the oracle's CC2."""
+    from paper_2103_08473_amd.exacc import CCSD
+    o, v, X, iters = 8, 40, 120, 30
+    eps, B = make_system(o, v, X, seed=3)
+    ref = oracle.solve(eps, B, o, max_iter=iters, tol=1e-10, cc2=True)
+    with CCSD(eps, B, o, tol=1e-10, cc2=1) as cc:
+        _, conv, hist = cc.solve(max_iter=iters)
+        t1, t2 = cc.amplitudes()
+    assert len(hist) == len(ref.history)
+    for (it, eg, rg), (_, eo, ro) in zip(hist, ref.history):
+        assert abs(eg - eo) <= 1e-10, (it, eg, eo)
+        assert abs(rg - ro) <= 1e-8 * max(1.0, ro), (it, rg, ro)
+    assert conv == ref.converged
+    assert max(np.abs(t1 - ref.t1).max(), np.abs(t2 - ref.t2).max()) <= 1e-10
+
+
 def test_one_electron_is_exact_at_first_step(lib):
     from paper_2103_08473_amd.exacc import CCSD
     eps, B = make_system(1, 9, 20, seed=4, sigma=0.1)

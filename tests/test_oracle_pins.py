@@ -93,6 +93,39 @@ def test_ccd_residual_is_brute_force_projection():
     np.testing.assert_allclose(S2, S2b, atol=1e-13, rtol=0)
 
 
+@pytest.mark.parametrize("o,v,X,seed", [(2, 4, 7, 0), (3, 4, 9, 3), (3, 5, 11, 5)])
+def test_cc2_residual_equals_second_quantisation(o, v, X, seed):
+    """CC2: singles = <mu1| e^-T H e^T |0> (T = T1 + T2), doubles =
+    <mu2| e^-T1 H e^T1 |0> + (e_a + e_b - e_i - e_j) t2, both by brute force."""
+    eps, B = make_system(o, v, X, seed=seed, sigma=0.3)
+    t1, t2 = make_amplitudes(o, v, seed=seed + 200, scale=0.15)
+    S1, S2 = oracle.cc2_residual(eps, build_integrals(B, o), t1, t2)
+    n = o + v
+    V = antisym(B, slice(0, n), slice(0, n), slice(0, n), slice(0, n))
+    _, S1b, _ = sq_brute.cc_residual(eps, V, o, t1, t2)
+    _, _, S2t1 = sq_brute.cc_residual(eps, V, o, t1, np.zeros_like(t2))
+    eo, ev = eps[:o], eps[o:]
+    D2 = ev[None, None, :, None] + ev[None, None, None, :] - eo[:, None, None, None] - eo[None, :, None, None]
+    assert np.abs(S2t1).max() > 0.05
+    np.testing.assert_allclose(S1, S1b, atol=1e-13, rtol=0)
+    np.testing.assert_allclose(S2, S2t1 + D2 * t2, atol=1e-13, rtol=0)
+    # and CC2 is not CCSD: the T2-quadratic and T1-T2 doubles terms are missing
+    _, S2ccsd = residual(eps, build_integrals(B, o), t1, t2)
+    assert np.abs(S2ccsd - S2).max() > 1e-3
+
+
+def test_cc2_solve_converges_between_mp2_and_ccsd_scale():
+    """A converged CC2 solve: residual below tol, and its energy differs from CCSD's."""
+    o, v, X = 4, 16, 40
+    eps, B = make_system(o, v, X, seed=21)
+    r2 = oracle.solve(eps, B, o, max_iter=80, tol=1e-11, cc2=True)
+    rs = oracle.solve(eps, B, o, max_iter=80, tol=1e-11)
+    assert r2.converged and rs.converged
+    S1, S2 = oracle.cc2_residual(eps, build_integrals(B, o), r2.t1, r2.t2)
+    assert max(np.abs(S1).max(), np.abs(S2).max()) < 1e-9
+    assert abs(r2.energy - rs.energy) > 1e-6
+
+
 def test_one_electron_degenerate_case():
     """nocc = 1: no doubles; canonical spinors make the reference exact (E = FCI = 0)."""
     eps, B = make_system(1, 9, 20, seed=4, sigma=0.1)
