@@ -18,7 +18,9 @@ Pins (tests/test_oracle_*.py, all CPU):
     real-factor limit, Jacobi and DIIS reaching the same fixed point;
   * the element-by-element residual (large sizes) == the full residual;
   * CCD (T1 = 0) for two electrons == CI over the reference and its doubles;
-  * CC2 residuals == their defining second-quantised projections.
+  * CC2 residuals == their defining second-quantised projections;
+  * perturbative triples (oracle/triples.py): W~, Z~ == the connected and
+    disconnected triples projections, E(+T) == fourth-order triples energy.
 """
 from .integrals import antisym, mulliken  # noqa: F401
 from .ccsd import (  # noqa: F401
@@ -26,3 +28,4 @@ from .ccsd import (  # noqa: F401
     residual, solve, tau, unpack_t2,
 )
 from .fci import fci_two_electron, fci_one_electron  # noqa: F401
+from .triples import triples_energies  # noqa: F401
