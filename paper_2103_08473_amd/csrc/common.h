@@ -104,6 +104,10 @@ void k_assemble_t1(const T* S1, const double* t1, const double* eps, int o, int 
 // CC2: Vt[a][i][P] += B^P_ai - Q[a][i][P] (the T1-dressed vo DF factor; Bt is [p][q][P])
 template <typename T>
 void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipStream_t s);
+// perturbative triples: (e4, e5) block partials of one occupied triple i<j<k
+int triples_blocks(int v);
+void k_triples_energy(const double* W, const double* Voovv, const double* t1, const double* eps, int i,
+                      int j, int k, int o, int v, double* partial, int nblk, hipStream_t s);
 // FP64 -> FP32, round to nearest even, nreal reals
 void k_cast(const double* in, float* out, int64_t nreal, hipStream_t s);
 int assemble_t2_blocks(int64_t npairs);

@@ -582,6 +582,63 @@ void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipS
   HIPCHECK(hipGetLastError());
 }
 
+// Perturbative triples, one occupied triple i<j<k (App. C): over all (a, b, c),
+//   W~ = W[a,b,c] + W[b,c,a] + W[c,a,b]                      (W: [a][b][c], v^3)
+//   Z~ = Z(a,b,c) + Z(c,a,b) + Z(b,c,a),  Z(a,b,c) = <ab||ij> t_k^c + <ab||jk> t_i^c
+//        + <ab||ki> t_j^c with <ab||xy> = conj(<xy||ab>) from Voovv [x][y][a][b]
+//   e4 += -|W~|^2 / D,  e5 += -Re(conj(Z~) W~) / D,  D = e_a + e_b + e_c - e_i - e_j - e_k.
+// Block partial sums (e4, e5) to part[2 * block].
+__global__ void triples_energy_kernel(const double* __restrict__ W, const double* __restrict__ Voovv,
+                                      const double* __restrict__ t1, const double* __restrict__ eps,
+                                      int i, int j, int k, int o, int v, double* __restrict__ part) {
+  const int64_t vv = (int64_t)v * v, v3 = vv * v, oo = (int64_t)o * o;
+  auto Wl = [&](int a, int b, int c) { return ld(W, (int64_t)a * vv + (int64_t)b * v + c); };
+  auto Vc = [&](int x, int y, int a, int b) {  // <ab||xy> = conj(<xy||ab>)
+    const z g = ld(Voovv, ((int64_t)x * o + y) * vv + (int64_t)a * v + b);
+    return z{g.x, -g.y};
+  };
+  auto Zf = [&](int a, int b, int c) {
+    z r = mul(Vc(i, j, a, b), ld(t1, (int64_t)k * v + c));
+    r = add(r, mul(Vc(j, k, a, b), ld(t1, (int64_t)i * v + c)));
+    return add(r, mul(Vc(k, i, a, b), ld(t1, (int64_t)j * v + c)));
+  };
+  (void)oo;
+  double e4 = 0, e5 = 0;
+  const double eo = eps[i] + eps[j] + eps[k];
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < v3; t += (int64_t)gridDim.x * TB) {
+    const int a = (int)(t / vv), b = (int)((t / v) % v), c = (int)(t % v);
+    const z w = add(Wl(a, b, c), add(Wl(b, c, a), Wl(c, a, b)));
+    const z zz = add(Zf(a, b, c), add(Zf(c, a, b), Zf(b, c, a)));
+    const double D = eps[o + a] + eps[o + b] + eps[o + c] - eo;
+    e4 -= (w.x * w.x + w.y * w.y) / D;
+    e5 -= (zz.x * w.x + zz.y * w.y) / D;
+  }
+  __shared__ double s4[TB], s5[TB];
+  s4[threadIdx.x] = e4;
+  s5[threadIdx.x] = e5;
+  __syncthreads();
+  for (int s = TB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      s4[threadIdx.x] += s4[threadIdx.x + s];
+      s5[threadIdx.x] += s5[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s4[0];
+    part[2 * blockIdx.x + 1] = s5[0];
+  }
+}
+
+int triples_blocks(int v) { return nblocks((int64_t)v * v * v, 2048); }
+
+void k_triples_energy(const double* W, const double* Voovv, const double* t1, const double* eps, int i,
+                      int j, int k, int o, int v, double* partial, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(triples_energy_kernel, dim3(nblk), dim3(TB), 0, s, W, Voovv, t1, eps, i, j, k, o, v,
+                     partial);
+  HIPCHECK(hipGetLastError());
+}
+
 template <typename T>
 void k_assemble_t1(const T* S1, const double* t1, const double* eps, int o, int v, double shift,
                    bool frozen, double* xt, double* e, double* s1_full, double* partial, hipStream_t s) {

@@ -814,6 +814,84 @@ static void reset_diis(Handle& h) {
   h.first_norm = -1.0;
 }
 
+// ------------------------------------------------------------------ perturbative triples
+// E(+T) and E((T)) of App. C at the current amplitudes (FP64).  The excitation
+// elements <ab||ie> = (ai|be) - (ae|bi) are built once from the DF factors for every
+// occupied i ([i][e][a][b], o v^3), then for each occupied triple i<j<k
+//   W[a][b][c] = sum_e (<ab||ie> t_jk^ec + <ab||je> t_ki^ec + <ab||ke> t_ij^ec)
+//              + sum_m (<am||ij> t_km^bc + <am||jk> t_im^bc + <am||ki> t_jm^bc)
+// with <am||ij> = -conj(<ij||ma>) from the stored ooov class, and the energy kernel
+// forms the cyclic sums W~, Z~ and the two energy terms.  Each triple's (e4, e5) is
+// reduced in a fixed order and the triples are summed on the host in order:
+// E = (1/6) sum_{i<j<k} sum_{abc} (the (1/36) sum over all ijk, abc).
+static void triples_impl(Handle& h, double* e4_out, double* e5_out) {
+  if (h.phase32) raise(EXACC_ERR_INVALID_ARG, "triples need FP64 integrals: the handle is still in its low-precision phase");
+  const int o = h.P.o, v = h.P.v;
+  *e4_out = 0.0;
+  *e5_out = 0.0;
+  if (o < 3 || v < 3) return;
+  const hipStream_t s = h.s;
+  const int64_t vv = (int64_t)v * v, v3 = vv * v, oov = (int64_t)o * o * v;
+  const int64_t ntrip = (int64_t)o * (o - 1) * (o - 2) / 6;
+  const int nblk = triples_blocks(v);
+  const size_t need = (size_t)(o * v3 + v3 + ntrip + nblk + 4) * 16;
+  size_t free_b = 0, total_b = 0;
+  HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+  if (need + (64u << 20) > free_b)
+    raise(EXACC_ERR_NOMEM, "triples: the <ab||ie> tiles (nocc * nvir^3 complex) do not fit in free device memory");
+  h.use();
+  double* Ve = h.dalloc(o * v3);
+  double* W = h.dalloc(v3);
+  double* part = h.dalloc(nblk);
+  double* tri = h.dalloc(ntrip);  // (e4, e5) per triple
+  struct Free {
+    Handle& h;
+    double** p[4];
+    ~Free() {
+      for (auto q : p) h.dfree(*q);
+    }
+  } fr{h, {&Ve, &W, &part, &tri}};
+  // full t2 [i][j][a][b] into H4 (an FP64 work array rebuilt every iteration)
+  k_unpack_full(h.x, h.x + 2 * (int64_t)o * v, nullptr, h.H4, o, v, s);
+  Views<double> b = bviews(h, h.Bt);
+  auto VeV = view(Ve, {o, v, v, v});
+  contract(s, "aiP,beP->ieab", ONE, b.Bvo, b.Bvv, false, VeV);
+  contract(s, "aeP,biP->ieab", MONE, b.Bvv, b.Bvo, true, VeV);
+  const double* T2 = h.H4;
+  auto Wv = view(W, {v, v, v});
+  auto Vsl = [&](int i) { return sview(Ve + 2 * (int64_t)i * v3, {v, v, v}, {vv, (int64_t)v, 1}); };
+  auto Tpair = [&](int j, int k) { return sview(h.H4 + 2 * ((int64_t)j * o + k) * vv, {v, v}, {(int64_t)v, 1}); };
+  auto Tone = [&](int k) { return sview(h.H4 + 2 * (int64_t)k * o * vv, {o, v, v}, {vv, (int64_t)v, 1}); };
+  auto Vm = [&](int i, int j) {  // <ij||ma> as [m][a]; the term uses -conj of it
+    return conj(sview(h.Vooov + 2 * ((int64_t)i * o + j) * o * v, {o, v}, {(int64_t)v, 1}));
+  };
+  (void)T2;
+  (void)oov;
+  int64_t t = 0;
+  for (int i = 0; i < o; ++i)
+    for (int j = i + 1; j < o; ++j)
+      for (int k = j + 1; k < o; ++k, ++t) {
+        contract(s, "eab,ec->abc", ONE, Vsl(i), Tpair(j, k), false, Wv);
+        contract(s, "eab,ec->abc", ONE, Vsl(j), Tpair(k, i), true, Wv);
+        contract(s, "eab,ec->abc", ONE, Vsl(k), Tpair(i, j), true, Wv);
+        contract(s, "ma,mbc->abc", MONE, Vm(i, j), Tone(k), true, Wv);
+        contract(s, "ma,mbc->abc", MONE, Vm(j, k), Tone(i), true, Wv);
+        contract(s, "ma,mbc->abc", MONE, Vm(k, i), Tone(j), true, Wv);
+        k_triples_energy(W, h.Voovv, h.x, h.eps, i, j, k, o, v, part, nblk, s);
+        k_reduce_sum(part, nblk, 2, tri + 2 * t, s);
+      }
+  std::vector<double> host(2 * ntrip);
+  HIPCHECK(hipMemcpyAsync(host.data(), tri, host.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  double e4 = 0, e5 = 0;
+  for (int64_t q = 0; q < ntrip; ++q) {
+    e4 += host[2 * q];
+    e5 += host[2 * q + 1];
+  }
+  *e4_out = e4 / 6.0;
+  *e5_out = (e4 + e5) / 6.0;
+}
+
 // ------------------------------------------------------------------ create
 static void validate_host_inputs(int o, int v, const double* eps) {
   double emax = -1e300, emin = 1e300;
@@ -1152,6 +1230,19 @@ int exacc_ccsd_residual(exacc_ccsd_t hh, double* s1, double* s2, int on_device) 
     if (s2) HIPCHECK(hipMemcpyAsync(s2, h.Tq, (size_t)h.P.oovv * 16, k, h.s));
     HIPCHECK(hipStreamSynchronize(h.s));
     timer_collect(h);
+    return (int)EXACC_OK;
+  });
+}
+
+int exacc_ccsd_triples(exacc_ccsd_t hh, double* e_plus_t, double* e_paren_t) {
+  return guarded([&] {
+    if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    h.use();
+    double e4 = 0, e5 = 0;
+    triples_impl(h, &e4, &e5);
+    if (e_plus_t) *e_plus_t = e4;
+    if (e_paren_t) *e_paren_t = e5;
     return (int)EXACC_OK;
   });
 }

@@ -65,6 +65,7 @@ def load():
     L.exacc_ccsd_get_amplitudes.argtypes = [P, P, P, I]
     L.exacc_ccsd_set_amplitudes.argtypes = [P, P, P, I]
     L.exacc_ccsd_residual.argtypes = [P, P, P, I]
+    L.exacc_ccsd_triples.argtypes = [P, dp, dp]
     L.exacc_ccsd_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p), dp, ip, I]
     L.exacc_ccsd_phase.argtypes = [P, ip, ip]
     L.exacc_ccsd_phase.restype = I
@@ -77,7 +78,7 @@ def load():
     L.exacc_last_error.restype = ctypes.c_char_p
     for f in ("exacc_ccsd_create", "exacc_ccsd_iterate", "exacc_ccsd_energy",
               "exacc_ccsd_get_amplitudes", "exacc_ccsd_set_amplitudes", "exacc_ccsd_residual",
-              "exacc_ccsd_stage_times", "exacc_ccsd_destroy"):
+              "exacc_ccsd_triples", "exacc_ccsd_stage_times", "exacc_ccsd_destroy"):
         getattr(L, f).restype = I
     _lib = L
     return L
@@ -219,6 +220,12 @@ class CCSD:
         r2 = np.zeros((o, o, v, v), np.complex128)
         _check(self.L.exacc_ccsd_residual(self.h, r1.ctypes.data, r2.ctypes.data, 0))
         return r1, r2
+
+    def triples(self):
+        """(E(+T), E((T))) at the current amplitudes (App. C), FP64, Hartree."""
+        e4, e5 = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        _check(self.L.exacc_ccsd_triples(self.h, ctypes.byref(e4), ctypes.byref(e5)))
+        return e4.value, e5.value
 
     def phase(self):
         """(next step runs FP32 contractions, FP64 iterations since the switch)."""

@@ -38,7 +38,14 @@ MODES = {"fp64": exacc.FP64, "mixed_fp32": exacc.MIXED_FP32, "mixed_bf16x3": exa
 SAMPLE_SEED, SAMPLE_RANDOM, SAMPLE_TOP = 2024, 1_000_000, 500_000
 
 
-def solve(eps_d, B_d, nocc, mode, tol, diis, max_iter, log, time_limit=None, **extra):
+def triples_flops(o, v, X):
+    """Algorithmic flops of exacc_ccsd_triples: the <ab||ie> tiles (2 o v^3 X complex
+    multiply-adds) and, per occupied triple, 3 v^4 + 3 o v^3 (8 flops each)."""
+    ntrip = o * (o - 1) * (o - 2) / 6
+    return 8.0 * (2.0 * o * v ** 3 * X + ntrip * (3.0 * v ** 4 + 3.0 * o * v ** 3))
+
+
+def solve(eps_d, B_d, nocc, mode, tol, diis, max_iter, log, time_limit=None, triples=False, **extra):
     import torch
     t0 = time.perf_counter()
     cc = exacc.CCSD(eps_d, B_d, nocc, precision=MODES[mode], tol=tol, diis_size=diis,
@@ -62,6 +69,15 @@ def solve(eps_d, B_d, nocc, mode, tol, diis, max_iter, log, time_limit=None, **e
             break
     torch.cuda.synchronize()
     t_iter = time.perf_counter() - t1
+    tri = None
+    if triples:
+        t0 = time.perf_counter()
+        e4, et = cc.triples()
+        dtt = time.perf_counter() - t0
+        o, v, X = nocc, eps_d.numel() - nocc, B_d.shape[0]
+        tri = {"E(+T)": e4, "E((T))": et, "seconds": round(dtt, 3),
+               "tflops": round(triples_flops(o, v, X) / dtt / 1e12, 3)}
+        log("  triples %s" % json.dumps(tri))
     t1a, t2a = cc.amplitudes()
     cc.close()
     low_t = [h[5] for h in hist if h[1] == "low"]
@@ -72,7 +88,7 @@ def solve(eps_d, B_d, nocc, mode, tol, diis, max_iter, log, time_limit=None, **e
             "s_per_low_iter": round(float(np.mean(low_t)), 4) if low_t else None,
             "s_per_fp64_iter": round(float(np.mean(hi_t)), 4) if hi_t else None,
             "residual": hist[-1][4] if hist else None,
-            "history": hist}, t1a, t2a
+            "triples": tri, "history": hist}, t1a, t2a
 
 
 def random_unique_t2(o, v, n, seed=SAMPLE_SEED):
@@ -124,6 +140,8 @@ def main():
                     help="width of the DF factor entries (default: the generator's size rule)")
     ap.add_argument("--save", default=None, help="keep E, t1 and a t2 sample of the first mode here")
     ap.add_argument("--ref", default=None, help="compare every mode with a solve kept by --save")
+    ap.add_argument("--triples", action="store_true",
+                    help="after each solve, E(+T) and E((T)) (App. C) with their time")
     ap.add_argument("--time-limit", type=float, default=None,
                     help="stop iterating once this many seconds have passed since start-up")
     args = ap.parse_args()
@@ -146,7 +164,7 @@ def main():
         log("solve %s" % mode)
         extra = {} if args.switch_tol is None else {"mixed_switch_tol": args.switch_tol}
         res, t1, t2 = solve(eps_d, B_d, o, mode, args.tol, args.diis, args.max_iter, log,
-                            time_limit=args.time_limit, **extra)
+                            time_limit=args.time_limit, triples=args.triples, **extra)
         if args.ref:
             res.update(compare_saved(args.ref, res, t1, t2, o, v))
         if args.save and not out["modes"]:

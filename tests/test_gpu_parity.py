@@ -141,6 +141,49 @@ def test_cc2_iterations_match_oracle(lib):
     assert max(np.abs(t1 - ref.t1).max(), np.abs(t2 - ref.t2).max()) <= 1e-10
 
 
+@pytest.mark.parametrize("o,v,X", [(3, 3, 7), (5, 12, 30), (6, 17, 40), (8, 20, 50)])
+def test_triples_match_oracle(lib, o, v, X):
+    """E(+T), E((T)) (App. C) at random amplitudes vs the oracle (pinned by brute force):
+    1e-12 of |E(+T)|."""
+    from oracle.integrals import antisym
+    from oracle.triples import triples_energies
+    from paper_2103_08473_amd.exacc import CCSD
+    say("triples case", o, v, X)
+    eps, B = make_system(o, v, X, seed=o * 100 + v, sigma=0.2)
+    t1, t2 = make_amplitudes(o, v, seed=3 + o, scale=0.1)
+    n = o + v
+    V = antisym(B, slice(0, n), slice(0, n), slice(0, n), slice(0, n))
+    e4, et = triples_energies(eps, V, o, t1, t2)
+    with CCSD(eps, B, o) as cc:
+        cc.set_amplitudes(t1, t2)
+        g4, gt = cc.triples()
+        r1, r2 = cc.amplitudes()
+    assert np.array_equal(r1, t1) and np.array_equal(r2, t2)
+    assert abs(e4) > 1e-6
+    assert abs(g4 - e4) <= 1e-12 * abs(e4)
+    assert abs(gt - et) <= 1e-12 * abs(e4)
+
+
+def test_ccsd_t_after_converged_solve(lib):
+    """CCSD(T): converged GPU CCSD plus GPU triples vs the oracle's solve plus triples."""
+    from oracle.integrals import antisym
+    from oracle.triples import triples_energies
+    from paper_2103_08473_amd.exacc import CCSD
+    o, v, X = 6, 24, 60
+    eps, B = make_system(o, v, X, seed=17)
+    ref = oracle.solve(eps, B, o, max_iter=80, tol=1e-11)
+    n = o + v
+    e4, et = triples_energies(eps, antisym(B, slice(0, n), slice(0, n), slice(0, n), slice(0, n)),
+                              o, ref.t1, ref.t2)
+    with CCSD(eps, B, o, tol=1e-11, max_iter=80) as cc:
+        e, conv, _ = cc.solve()
+        g4, gt = cc.triples()
+    assert conv and ref.converged
+    assert abs(e - ref.energy) <= 1e-10
+    assert abs(g4 - e4) <= 1e-10 and abs(gt - et) <= 1e-10
+    say("  CCSD %.10f  E(+T) %.3e  E((T)) %.3e" % (e.real, g4, gt))
+
+
 def test_one_electron_is_exact_at_first_step(lib):
     from paper_2103_08473_amd.exacc import CCSD
     eps, B = make_system(1, 9, 20, seed=4, sigma=0.1)
