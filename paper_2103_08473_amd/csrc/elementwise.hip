@@ -582,16 +582,19 @@ void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipS
   HIPCHECK(hipGetLastError());
 }
 
-// Perturbative triples, one occupied triple i<j<k (App. C): over all (a, b, c),
-//   W~ = W[a,b,c] + W[b,c,a] + W[c,a,b]                      (W: [a][b][c], v^3)
+// Perturbative triples (App. C), a batch of occupied triples (i0 + y, j, k), y < ni,
+// i0 + ni <= j < k, with W[y][a][b][c] (v^3 each).  Over all (a, b, c):
+//   W~ = W[a,b,c] + W[b,c,a] + W[c,a,b]
 //   Z~ = Z(a,b,c) + Z(c,a,b) + Z(b,c,a),  Z(a,b,c) = <ab||ij> t_k^c + <ab||jk> t_i^c
 //        + <ab||ki> t_j^c with <ab||xy> = conj(<xy||ab>) from Voovv [x][y][a][b]
 //   e4 += -|W~|^2 / D,  e5 += -Re(conj(Z~) W~) / D,  D = e_a + e_b + e_c - e_i - e_j - e_k.
-// Block partial sums (e4, e5) to part[2 * block].
-__global__ void triples_energy_kernel(const double* __restrict__ W, const double* __restrict__ Voovv,
+// Block partial sums (e4, e5) to part[2 * (y * gridDim.x + block)].
+__global__ void triples_energy_kernel(const double* __restrict__ Wb, const double* __restrict__ Voovv,
                                       const double* __restrict__ t1, const double* __restrict__ eps,
-                                      int i, int j, int k, int o, int v, double* __restrict__ part) {
-  const int64_t vv = (int64_t)v * v, v3 = vv * v, oo = (int64_t)o * o;
+                                      int i0, int j, int k, int o, int v, double* __restrict__ part) {
+  const int64_t vv = (int64_t)v * v, v3 = vv * v;
+  const int i = i0 + (int)blockIdx.y;
+  const double* __restrict__ W = Wb + 2 * (int64_t)blockIdx.y * v3;
   auto Wl = [&](int a, int b, int c) { return ld(W, (int64_t)a * vv + (int64_t)b * v + c); };
   auto Vc = [&](int x, int y, int a, int b) {  // <ab||xy> = conj(<xy||ab>)
     const z g = ld(Voovv, ((int64_t)x * o + y) * vv + (int64_t)a * v + b);
@@ -602,7 +605,6 @@ __global__ void triples_energy_kernel(const double* __restrict__ W, const double
     r = add(r, mul(Vc(j, k, a, b), ld(t1, (int64_t)i * v + c)));
     return add(r, mul(Vc(k, i, a, b), ld(t1, (int64_t)j * v + c)));
   };
-  (void)oo;
   double e4 = 0, e5 = 0;
   const double eo = eps[i] + eps[j] + eps[k];
   for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < v3; t += (int64_t)gridDim.x * TB) {
@@ -625,17 +627,50 @@ __global__ void triples_energy_kernel(const double* __restrict__ W, const double
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = s4[0];
-    part[2 * blockIdx.x + 1] = s5[0];
+    const int64_t q = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    part[2 * q] = s4[0];
+    part[2 * q + 1] = s5[0];
   }
 }
 
-int triples_blocks(int v) { return nblocks((int64_t)v * v * v, 2048); }
+// One block per triple of the batch: the nblk partials in a fixed order, to
+// out[((i0 + y) * o + j) * o + k] (two values).
+__global__ void triples_reduce_kernel(const double* __restrict__ part, int nblk, int i0, int j, int k,
+                                      int o, double* __restrict__ out) {
+  __shared__ double s4[TB], s5[TB];
+  const double* p = part + 2 * (int64_t)blockIdx.x * nblk;
+  double a = 0, b = 0;
+  for (int q = threadIdx.x; q < nblk; q += TB) {
+    a += p[2 * q];
+    b += p[2 * q + 1];
+  }
+  s4[threadIdx.x] = a;
+  s5[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = TB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      s4[threadIdx.x] += s4[threadIdx.x + s];
+      s5[threadIdx.x] += s5[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t idx = ((int64_t)(i0 + blockIdx.x) * o + j) * o + k;
+    out[2 * idx] = s4[0];
+    out[2 * idx + 1] = s5[0];
+  }
+}
 
-void k_triples_energy(const double* W, const double* Voovv, const double* t1, const double* eps, int i,
-                      int j, int k, int o, int v, double* partial, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL(triples_energy_kernel, dim3(nblk), dim3(TB), 0, s, W, Voovv, t1, eps, i, j, k, o, v,
-                     partial);
+int triples_blocks(int v) { return nblocks((int64_t)v * v * v, 1024); }
+
+void k_triples_energy(const double* W, const double* Voovv, const double* t1, const double* eps, int i0,
+                      int ni, int j, int k, int o, int v, double* partial, int nblk, double* out,
+                      hipStream_t s) {
+  if (ni <= 0) return;
+  hipLaunchKernelGGL(triples_energy_kernel, dim3(nblk, ni), dim3(TB), 0, s, W, Voovv, t1, eps, i0, j, k,
+                     o, v, partial);
+  HIPCHECK(hipGetLastError());
+  hipLaunchKernelGGL(triples_reduce_kernel, dim3(ni), dim3(TB), 0, s, partial, nblk, i0, j, k, o, out);
   HIPCHECK(hipGetLastError());
 }
 

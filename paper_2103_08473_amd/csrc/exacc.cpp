@@ -817,33 +817,37 @@ static void reset_diis(Handle& h) {
 // ------------------------------------------------------------------ perturbative triples
 // E(+T) and E((T)) of App. C at the current amplitudes (FP64).  The excitation
 // elements <ab||ie> = (ai|be) - (ae|bi) are built once from the DF factors for every
-// occupied i ([i][e][a][b], o v^3), then for each occupied triple i<j<k
-//   W[a][b][c] = sum_e (<ab||ie> t_jk^ec + <ab||je> t_ki^ec + <ab||ke> t_ij^ec)
-//              + sum_m (<am||ij> t_km^bc + <am||jk> t_im^bc + <am||ki> t_jm^bc)
-// with <am||ij> = -conj(<ij||ma>) from the stored ooov class, and the energy kernel
-// forms the cyclic sums W~, Z~ and the two energy terms.  Each triple's (e4, e5) is
-// reduced in a fixed order and the triples are summed on the host in order:
+// occupied i ([i][a][b][e], o v^3).  Then for each occupied pair j<k and a batch of
+// i<j (the paper's unique triples, batched over i)
+//   W[i][a][b][c] = sum_e (<ab||ie> t_jk^ec + <ab||je> t_ki^ec + <ab||ke> t_ij^ec)
+//                 + sum_m (<am||ij> t_km^bc + <am||jk> t_im^bc + <am||ki> t_jm^bc)
+// (six GETTs; <am||xy> = -conj(<xy||ma>) from the stored ooov class), and the energy
+// kernel forms the cyclic sums W~, Z~ and the two energy terms of each triple, reduced
+// in a fixed order.  The host sums the triples in order:
 // E = (1/6) sum_{i<j<k} sum_{abc} (the (1/36) sum over all ijk, abc).
 static void triples_impl(Handle& h, double* e4_out, double* e5_out) {
-  if (h.phase32) raise(EXACC_ERR_INVALID_ARG, "triples need FP64 integrals: the handle is still in its low-precision phase");
+  if (h.phase32)
+    raise(EXACC_ERR_INVALID_ARG,
+          "triples need FP64 integrals: the handle is still in its low-precision phase");
   const int o = h.P.o, v = h.P.v;
   *e4_out = 0.0;
   *e5_out = 0.0;
   if (o < 3 || v < 3) return;
   const hipStream_t s = h.s;
-  const int64_t vv = (int64_t)v * v, v3 = vv * v, oov = (int64_t)o * o * v;
-  const int64_t ntrip = (int64_t)o * (o - 1) * (o - 2) / 6;
+  const int64_t vv = (int64_t)v * v, v3 = vv * v, ooo = (int64_t)o * o * o;
   const int nblk = triples_blocks(v);
-  const size_t need = (size_t)(o * v3 + v3 + ntrip + nblk + 4) * 16;
   size_t free_b = 0, total_b = 0;
   HIPCHECK(hipMemGetInfo(&free_b, &total_b));
-  if (need + (64u << 20) > free_b)
+  const size_t fixed = (size_t)(o * v3 + ooo + (int64_t)(o - 2) * nblk + 4) * 16 + (256u << 20);
+  if (fixed + (size_t)v3 * 16 > free_b)
     raise(EXACC_ERR_NOMEM, "triples: the <ab||ie> tiles (nocc * nvir^3 complex) do not fit in free device memory");
+  // W rows (one per triple of a batch): what fits beside the tiles, at most o - 2
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(o - 2, (int64_t)((free_b - fixed) / 2 / (v3 * 16))));
   h.use();
   double* Ve = h.dalloc(o * v3);
-  double* W = h.dalloc(v3);
-  double* part = h.dalloc(nblk);
-  double* tri = h.dalloc(ntrip);  // (e4, e5) per triple
+  double* W = h.dalloc(cap * v3);
+  double* part = h.dalloc(cap * nblk);
+  double* tri = h.dalloc(ooo);  // (e4, e5) at [i][j][k]
   struct Free {
     Handle& h;
     double** p[4];
@@ -854,40 +858,57 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out) {
   // full t2 [i][j][a][b] into H4 (an FP64 work array rebuilt every iteration)
   k_unpack_full(h.x, h.x + 2 * (int64_t)o * v, nullptr, h.H4, o, v, s);
   Views<double> b = bviews(h, h.Bt);
+  // [i][a][b][e]: e contiguous, so the W GETTs read both operands along K
   auto VeV = view(Ve, {o, v, v, v});
-  contract(s, "aiP,beP->ieab", ONE, b.Bvo, b.Bvv, false, VeV);
-  contract(s, "aeP,biP->ieab", MONE, b.Bvv, b.Bvo, true, VeV);
-  const double* T2 = h.H4;
-  auto Wv = view(W, {v, v, v});
+  contract(s, "aiP,beP->iabe", ONE, b.Bvo, b.Bvv, false, VeV);
+  contract(s, "aeP,biP->iabe", MONE, b.Bvv, b.Bvo, true, VeV);
+  double* T2 = h.H4;
+  const int64_t ovv = (int64_t)o * vv, oov = (int64_t)o * o * v, ov = (int64_t)o * v;
   auto Vsl = [&](int i) { return sview(Ve + 2 * (int64_t)i * v3, {v, v, v}, {vv, (int64_t)v, 1}); };
-  auto Tpair = [&](int j, int k) { return sview(h.H4 + 2 * ((int64_t)j * o + k) * vv, {v, v}, {(int64_t)v, 1}); };
-  auto Tone = [&](int k) { return sview(h.H4 + 2 * (int64_t)k * o * vv, {o, v, v}, {vv, (int64_t)v, 1}); };
-  auto Vm = [&](int i, int j) {  // <ij||ma> as [m][a]; the term uses -conj of it
-    return conj(sview(h.Vooov + 2 * ((int64_t)i * o + j) * o * v, {o, v}, {(int64_t)v, 1}));
+  // t_jk^{ce} as [c][e] (e contiguous); t_jk^{ec} = -t_jk^{ce}
+  auto Tpair = [&](int j, int k) { return sview(T2 + 2 * ((int64_t)j * o + k) * vv, {v, v}, {(int64_t)v, 1}); };
+  auto Tone = [&](int k) { return sview(T2 + 2 * (int64_t)k * ovv, {o, v, v}, {vv, (int64_t)v, 1}); };
+  auto Vm = [&](int i, int j) {  // <ij||ma> as [m][a]; the terms use -conj of it
+    return conj(sview(h.Vooov + 2 * ((int64_t)i * o + j) * ov, {o, v}, {(int64_t)v, 1}));
   };
-  (void)T2;
-  (void)oov;
-  int64_t t = 0;
-  for (int i = 0; i < o; ++i)
-    for (int j = i + 1; j < o; ++j)
-      for (int k = j + 1; k < o; ++k, ++t) {
-        contract(s, "eab,ec->abc", ONE, Vsl(i), Tpair(j, k), false, Wv);
-        contract(s, "eab,ec->abc", ONE, Vsl(j), Tpair(k, i), true, Wv);
-        contract(s, "eab,ec->abc", ONE, Vsl(k), Tpair(i, j), true, Wv);
-        contract(s, "ma,mbc->abc", MONE, Vm(i, j), Tone(k), true, Wv);
-        contract(s, "ma,mbc->abc", MONE, Vm(j, k), Tone(i), true, Wv);
-        contract(s, "ma,mbc->abc", MONE, Vm(k, i), Tone(j), true, Wv);
-        k_triples_energy(W, h.Voovv, h.x, h.eps, i, j, k, o, v, part, nblk, s);
-        k_reduce_sum(part, nblk, 2, tri + 2 * t, s);
+  for (int k = 2; k < o; ++k)
+    for (int j = 1; j < k; ++j)
+      for (int i0 = 0; i0 < j; i0 += (int)cap) {
+        const int ni = (int)std::min<int64_t>(cap, j - i0);
+        auto Wv = view(W, {ni, v, v, v});
+        // sum_e <ab||ie> t_jk^ec = -sum_e <ab||ie> t_jk^ce, i over the batch
+        contract(s, "iabe,ce->iabc", MONE, sview(Ve + 2 * (int64_t)i0 * v3, {ni, v, v, v}, {v3, vv, (int64_t)v, 1}),
+                 Tpair(j, k), false, Wv);
+        // sum_e <ab||je> t_ki^ec, t_ki^ce = T2[k][i][c][e]
+        contract(s, "abe,ice->iabc", MONE, Vsl(j),
+                 sview(T2 + 2 * ((int64_t)k * o + i0) * vv, {ni, v, v}, {vv, (int64_t)v, 1}), true, Wv);
+        // sum_e <ab||ke> t_ij^ec, t_ij^ce = T2[i][j][c][e]
+        contract(s, "abe,ice->iabc", MONE, Vsl(k),
+                 sview(T2 + 2 * ((int64_t)i0 * o + j) * vv, {ni, v, v}, {ovv, (int64_t)v, 1}), true, Wv);
+        // sum_m <am||ij> t_km^bc
+        contract(s, "ima,mbc->iabc", MONE,
+                 conj(sview(h.Vooov + 2 * ((int64_t)i0 * o + j) * ov, {ni, o, v}, {oov, (int64_t)v, 1})),
+                 Tone(k), true, Wv);
+        // sum_m <am||jk> t_im^bc
+        contract(s, "ma,imbc->iabc", MONE, Vm(j, k),
+                 sview(T2 + 2 * (int64_t)i0 * ovv, {ni, o, v, v}, {ovv, vv, (int64_t)v, 1}), true, Wv);
+        // sum_m <am||ki> t_jm^bc
+        contract(s, "ima,mbc->iabc", MONE,
+                 conj(sview(h.Vooov + 2 * ((int64_t)k * o + i0) * ov, {ni, o, v}, {ov, (int64_t)v, 1})),
+                 Tone(j), true, Wv);
+        k_triples_energy(W, h.Voovv, h.x, h.eps, i0, ni, j, k, o, v, part, nblk, tri, s);
       }
-  std::vector<double> host(2 * ntrip);
+  std::vector<double> host(2 * ooo);
   HIPCHECK(hipMemcpyAsync(host.data(), tri, host.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
   double e4 = 0, e5 = 0;
-  for (int64_t q = 0; q < ntrip; ++q) {
-    e4 += host[2 * q];
-    e5 += host[2 * q + 1];
-  }
+  for (int i = 0; i < o; ++i)
+    for (int j = i + 1; j < o; ++j)
+      for (int k = j + 1; k < o; ++k) {
+        const int64_t q = ((int64_t)i * o + j) * o + k;
+        e4 += host[2 * q];
+        e5 += host[2 * q + 1];
+      }
   *e4_out = e4 / 6.0;
   *e5_out = (e4 + e5) / 6.0;
 }
