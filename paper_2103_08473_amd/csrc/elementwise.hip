@@ -607,13 +607,15 @@ __global__ void triples_energy_kernel(const double* __restrict__ Wb, const doubl
   };
   double e4 = 0, e5 = 0;
   const double eo = eps[i] + eps[j] + eps[k];
+  // W~ and Z~ are antisymmetric in (a, b, c): only a < b < c is evaluated, with weight 6
   for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < v3; t += (int64_t)gridDim.x * TB) {
     const int a = (int)(t / vv), b = (int)((t / v) % v), c = (int)(t % v);
+    if (!(a < b && b < c)) continue;
     const z w = add(Wl(a, b, c), add(Wl(b, c, a), Wl(c, a, b)));
     const z zz = add(Zf(a, b, c), add(Zf(c, a, b), Zf(b, c, a)));
     const double D = eps[o + a] + eps[o + b] + eps[o + c] - eo;
-    e4 -= (w.x * w.x + w.y * w.y) / D;
-    e5 -= (zz.x * w.x + zz.y * w.y) / D;
+    e4 -= 6.0 * (w.x * w.x + w.y * w.y) / D;
+    e5 -= 6.0 * (zz.x * w.x + zz.y * w.y) / D;
   }
   __shared__ double s4[TB], s5[TB];
   s4[threadIdx.x] = e4;
