@@ -128,15 +128,16 @@ int exacc_ccsd_residual(exacc_ccsd_t h, double* s1, double* s2, int ptr_on_devic
  * equations for perturbative triples; the paper's NOTRIPLES keyword turns
  * them off, here they are computed only on request).  *e_plus_t = E(+T), the
  * fourth-order term; *e_paren_t = E((T)) = E(+T) plus the singles-triples
- * term (either pointer may be NULL).  Complex spinors: W is formed with the
- * excitation elements <ab||ie>, <am||ij> (the complex conjugates of the
- * printed ones) and the singles-triples term has the standard CCSD(T) sign.
+ * term; *e_minus_t = E(-T) = E(+T) plus the Y-intermediate term (any pointer
+ * may be NULL).  Complex spinors: W is formed with the excitation elements
+ * <ab||ie>, <am||ij> (the complex conjugates of the printed ones) and the
+ * singles-triples term of E((T)) has the standard CCSD(T) sign.
  * FP64; needs the FP64 phase (INVALID_ARG while a mixed-precision handle is
  * still in its low-precision phase).  Temporary device memory: nocc * nvir^3
  * complex values for the <ab||ie> tiles plus nvir^3 for W, allocated and
  * freed inside the call (NOMEM if they do not fit).  Zero for nocc < 3 or
  * nvir < 3.  The amplitudes and the iteration state are not changed. */
-int exacc_ccsd_triples(exacc_ccsd_t h, double* e_plus_t, double* e_paren_t);
+int exacc_ccsd_triples(exacc_ccsd_t h, double* e_plus_t, double* e_paren_t, double* e_minus_t);
 
 /* Accumulated device time in ms of each stage since create (or the last
  * reset), measured with HIP events on the handle's stream; requires

@@ -23,7 +23,12 @@ second quantisation, not against this module):
   energy where the fifth-order singles-triples term lowers it, so the sign is
   read as garbled.  The term is half of the fifth-order perturbation-theory
   singles-triples energy 2 Re sum_T <0|T1^+ W_N|T><T|W_N T2|0> / (E_0 - E_T).
-* E(-T) (the Y intermediate) is not implemented here.
+* Y~ = Y^abc + Y^cab + Y^bca with the printed Y equals the triples projection of
+  e^(T1+T2) |0> (the disconnected triples T1 T2 + T1^3/6).
+* E(-T) = E(+T) + (1/36) sum Re(conj(Y~) W~), as printed (one factor conjugated).
+  At lowest order Y~ ~ -Z~/D, so this term and the singles-triples term of
+  E((T)) carry the same sign, which is what makes the plus here and the minus
+  above one consistent reading.
 """
 import numpy as np
 
@@ -55,6 +60,16 @@ def triples_Z(V, nocc, t1):
     return Z + Z.transpose(0, 1, 2, 5, 3, 4) + Z.transpose(0, 1, 2, 4, 5, 3)
 
 
+def triples_Y(t1, t2):
+    """Y~[i,j,k,a,b,c] = Y^abc + Y^cab + Y^bca with the printed Y."""
+    Y = (np.einsum('ia,jb,kc->ijkabc', t1, t1, t1) - np.einsum('ja,ib,kc->ijkabc', t1, t1, t1)
+         + np.einsum('ja,kb,ic->ijkabc', t1, t1, t1) - np.einsum('ka,jb,ic->ijkabc', t1, t1, t1)
+         + np.einsum('ka,ib,jc->ijkabc', t1, t1, t1) - np.einsum('ia,kb,jc->ijkabc', t1, t1, t1)) / 3.0
+    Y += (np.einsum('ijab,kc->ijkabc', t2, t1) + np.einsum('jkab,ic->ijkabc', t2, t1)
+          + np.einsum('kiab,jc->ijkabc', t2, t1))
+    return Y + Y.transpose(0, 1, 2, 5, 3, 4) + Y.transpose(0, 1, 2, 4, 5, 3)
+
+
 def triples_denominator(eps, nocc):
     eo, ev = _split(eps, nocc)
     return (ev[None, None, None, :, None, None] + ev[None, None, None, None, :, None]
@@ -63,14 +78,16 @@ def triples_denominator(eps, nocc):
 
 
 def triples_energies(eps, V, nocc, t1, t2):
-    """Return (E(+T), E((T))) for amplitudes t1, t2 (real parts; Hartree)."""
+    """Return (E(+T), E((T)), E(-T)) for amplitudes t1, t2 (real parts; Hartree)."""
     o = nocc
     v = eps.size - o
     if o < 3 or v < 3:
-        return 0.0, 0.0          # no triple excitation exists
+        return 0.0, 0.0, 0.0     # no triple excitation exists
     D = triples_denominator(eps, o)
     Wt = triples_W(V, o, t2)
     Zt = triples_Z(V, o, t1)
+    Yt = triples_Y(t1, t2)
     e4 = -float((np.abs(Wt) ** 2 / D).sum()) / 36.0
     e5 = -float((np.conj(Zt) * Wt / D).real.sum()) / 36.0
-    return e4, e4 + e5
+    ey = float((np.conj(Yt) * Wt).real.sum()) / 36.0
+    return e4, e4 + e5, e4 + ey

@@ -104,12 +104,12 @@ void k_assemble_t1(const T* S1, const double* t1, const double* eps, int o, int 
 // CC2: Vt[a][i][P] += B^P_ai - Q[a][i][P] (the T1-dressed vo DF factor; Bt is [p][q][P])
 template <typename T>
 void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipStream_t s);
-// perturbative triples: (e4, e5) of the occupied triples (i0 + y, j, k), y < ni, from
-// W[y][a][b][c]; written to out[((i0 + y) * o + j) * o + k] (two values each)
+// perturbative triples: (e4, e5, ey) of the occupied triples (i0 + y, j, k), y < ni, from
+// W[y][a][b][c] and the full T2; written to out[4 * (((i0 + y) * o + j) * o + k)]
 int triples_blocks(int v);
-void k_triples_energy(const double* W, const double* Voovv, const double* t1, const double* eps, int i0,
-                      int ni, int j, int k, int o, int v, double* partial, int nblk, double* out,
-                      hipStream_t s);
+void k_triples_energy(const double* W, const double* Voovv, const double* T2, const double* t1,
+                      const double* eps, int i0, int ni, int j, int k, int o, int v, double* partial,
+                      int nblk, double* out, hipStream_t s);
 // FP64 -> FP32, round to nearest even, nreal reals
 void k_cast(const double* in, float* out, int64_t nreal, hipStream_t s);
 int assemble_t2_blocks(int64_t npairs);

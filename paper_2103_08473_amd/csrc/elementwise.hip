@@ -583,15 +583,22 @@ void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipS
 }
 
 // Perturbative triples (App. C), a batch of occupied triples (i0 + y, j, k), y < ni,
-// i0 + ni <= j < k, with W[y][a][b][c] (v^3 each).  Over all (a, b, c):
+// i0 + ni <= j < k, with W[y][a][b][c] (v^3 each) and the full T2 [i][j][a][b].
+// W~, Z~ and Y~ are fully antisymmetric in (a, b, c), so only a < b < c is
+// evaluated, with weight 6:
 //   W~ = W[a,b,c] + W[b,c,a] + W[c,a,b]
 //   Z~ = Z(a,b,c) + Z(c,a,b) + Z(b,c,a),  Z(a,b,c) = <ab||ij> t_k^c + <ab||jk> t_i^c
 //        + <ab||ki> t_j^c with <ab||xy> = conj(<xy||ab>) from Voovv [x][y][a][b]
-//   e4 += -|W~|^2 / D,  e5 += -Re(conj(Z~) W~) / D,  D = e_a + e_b + e_c - e_i - e_j - e_k.
-// Block partial sums (e4, e5) to part[2 * (y * gridDim.x + block)].
+//   Y~ = Y(a,b,c) + Y(c,a,b) + Y(b,c,a),  Y(a,b,c) = (1/3) sum over the permutations p
+//        of (i,j,k) of sign(p) t_p1^a t_p2^b t_p3^c + t_ij^ab t_k^c + t_jk^ab t_i^c
+//        + t_ki^ab t_j^c
+//   e4 += -6 |W~|^2 / D,  e5 += -6 Re(conj(Z~) W~) / D,  ey += 6 Re(conj(Y~) W~),
+//   D = e_a + e_b + e_c - e_i - e_j - e_k.
+// Block partial sums (e4, e5, ey) to part[4 * (y * gridDim.x + block)].
 __global__ void triples_energy_kernel(const double* __restrict__ Wb, const double* __restrict__ Voovv,
-                                      const double* __restrict__ t1, const double* __restrict__ eps,
-                                      int i0, int j, int k, int o, int v, double* __restrict__ part) {
+                                      const double* __restrict__ T2, const double* __restrict__ t1,
+                                      const double* __restrict__ eps, int i0, int j, int k, int o, int v,
+                                      double* __restrict__ part) {
   const int64_t vv = (int64_t)v * v, v3 = vv * v;
   const int i = i0 + (int)blockIdx.y;
   const double* __restrict__ W = Wb + 2 * (int64_t)blockIdx.y * v3;
@@ -600,77 +607,99 @@ __global__ void triples_energy_kernel(const double* __restrict__ Wb, const doubl
     const z g = ld(Voovv, ((int64_t)x * o + y) * vv + (int64_t)a * v + b);
     return z{g.x, -g.y};
   };
+  auto T1 = [&](int x, int a) { return ld(t1, (int64_t)x * v + a); };
+  auto Tt = [&](int x, int y, int a, int b) { return ld(T2, ((int64_t)x * o + y) * vv + (int64_t)a * v + b); };
   auto Zf = [&](int a, int b, int c) {
-    z r = mul(Vc(i, j, a, b), ld(t1, (int64_t)k * v + c));
-    r = add(r, mul(Vc(j, k, a, b), ld(t1, (int64_t)i * v + c)));
-    return add(r, mul(Vc(k, i, a, b), ld(t1, (int64_t)j * v + c)));
+    z r = mul(Vc(i, j, a, b), T1(k, c));
+    r = add(r, mul(Vc(j, k, a, b), T1(i, c)));
+    return add(r, mul(Vc(k, i, a, b), T1(j, c)));
   };
-  double e4 = 0, e5 = 0;
+  auto Yf = [&](int a, int b, int c) {
+    z d = mul(mul(T1(i, a), T1(j, b)), T1(k, c));
+    d = sub(d, mul(mul(T1(j, a), T1(i, b)), T1(k, c)));
+    d = add(d, mul(mul(T1(j, a), T1(k, b)), T1(i, c)));
+    d = sub(d, mul(mul(T1(k, a), T1(j, b)), T1(i, c)));
+    d = add(d, mul(mul(T1(k, a), T1(i, b)), T1(j, c)));
+    d = sub(d, mul(mul(T1(i, a), T1(k, b)), T1(j, c)));
+    z r = scal(1.0 / 3.0, d);
+    r = add(r, mul(Tt(i, j, a, b), T1(k, c)));
+    r = add(r, mul(Tt(j, k, a, b), T1(i, c)));
+    return add(r, mul(Tt(k, i, a, b), T1(j, c)));
+  };
+  double e4 = 0, e5 = 0, ey = 0;
   const double eo = eps[i] + eps[j] + eps[k];
-  // W~ and Z~ are antisymmetric in (a, b, c): only a < b < c is evaluated, with weight 6
   for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < v3; t += (int64_t)gridDim.x * TB) {
     const int a = (int)(t / vv), b = (int)((t / v) % v), c = (int)(t % v);
     if (!(a < b && b < c)) continue;
     const z w = add(Wl(a, b, c), add(Wl(b, c, a), Wl(c, a, b)));
     const z zz = add(Zf(a, b, c), add(Zf(c, a, b), Zf(b, c, a)));
+    const z yy = add(Yf(a, b, c), add(Yf(c, a, b), Yf(b, c, a)));
     const double D = eps[o + a] + eps[o + b] + eps[o + c] - eo;
     e4 -= 6.0 * (w.x * w.x + w.y * w.y) / D;
     e5 -= 6.0 * (zz.x * w.x + zz.y * w.y) / D;
+    ey += 6.0 * (yy.x * w.x + yy.y * w.y);
   }
-  __shared__ double s4[TB], s5[TB];
+  __shared__ double s4[TB], s5[TB], sy[TB];
   s4[threadIdx.x] = e4;
   s5[threadIdx.x] = e5;
+  sy[threadIdx.x] = ey;
   __syncthreads();
   for (int s = TB / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
       s4[threadIdx.x] += s4[threadIdx.x + s];
       s5[threadIdx.x] += s5[threadIdx.x + s];
+      sy[threadIdx.x] += sy[threadIdx.x + s];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     const int64_t q = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    part[2 * q] = s4[0];
-    part[2 * q + 1] = s5[0];
+    part[4 * q] = s4[0];
+    part[4 * q + 1] = s5[0];
+    part[4 * q + 2] = sy[0];
   }
 }
 
 // One block per triple of the batch: the nblk partials in a fixed order, to
-// out[((i0 + y) * o + j) * o + k] (two values).
+// out[4 * (((i0 + y) * o + j) * o + k)] (three values).
 __global__ void triples_reduce_kernel(const double* __restrict__ part, int nblk, int i0, int j, int k,
                                       int o, double* __restrict__ out) {
-  __shared__ double s4[TB], s5[TB];
-  const double* p = part + 2 * (int64_t)blockIdx.x * nblk;
-  double a = 0, b = 0;
+  __shared__ double s4[TB], s5[TB], sy[TB];
+  const double* p = part + 4 * (int64_t)blockIdx.x * nblk;
+  double a = 0, b = 0, c = 0;
   for (int q = threadIdx.x; q < nblk; q += TB) {
-    a += p[2 * q];
-    b += p[2 * q + 1];
+    a += p[4 * q];
+    b += p[4 * q + 1];
+    c += p[4 * q + 2];
   }
   s4[threadIdx.x] = a;
   s5[threadIdx.x] = b;
+  sy[threadIdx.x] = c;
   __syncthreads();
   for (int s = TB / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
       s4[threadIdx.x] += s4[threadIdx.x + s];
       s5[threadIdx.x] += s5[threadIdx.x + s];
+      sy[threadIdx.x] += sy[threadIdx.x + s];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     const int64_t idx = ((int64_t)(i0 + blockIdx.x) * o + j) * o + k;
-    out[2 * idx] = s4[0];
-    out[2 * idx + 1] = s5[0];
+    out[4 * idx] = s4[0];
+    out[4 * idx + 1] = s5[0];
+    out[4 * idx + 2] = sy[0];
   }
 }
 
 int triples_blocks(int v) { return nblocks((int64_t)v * v * v, 1024); }
 
-void k_triples_energy(const double* W, const double* Voovv, const double* t1, const double* eps, int i0,
-                      int ni, int j, int k, int o, int v, double* partial, int nblk, double* out,
-                      hipStream_t s) {
+void k_triples_energy(const double* W, const double* Voovv, const double* T2, const double* t1,
+                      const double* eps, int i0, int ni, int j, int k, int o, int v, double* partial,
+                      int nblk, double* out, hipStream_t s) {
   if (ni <= 0) return;
-  hipLaunchKernelGGL(triples_energy_kernel, dim3(nblk, ni), dim3(TB), 0, s, W, Voovv, t1, eps, i0, j, k,
-                     o, v, partial);
+  hipLaunchKernelGGL(triples_energy_kernel, dim3(nblk, ni), dim3(TB), 0, s, W, Voovv, T2, t1, eps, i0, j,
+                     k, o, v, partial);
   HIPCHECK(hipGetLastError());
   hipLaunchKernelGGL(triples_reduce_kernel, dim3(ni), dim3(TB), 0, s, partial, nblk, i0, j, k, o, out);
   HIPCHECK(hipGetLastError());

@@ -822,23 +822,24 @@ static void reset_diis(Handle& h) {
 //   W[i][a][b][c] = sum_e (<ab||ie> t_jk^ec + <ab||je> t_ki^ec + <ab||ke> t_ij^ec)
 //                 + sum_m (<am||ij> t_km^bc + <am||jk> t_im^bc + <am||ki> t_jm^bc)
 // (six GETTs; <am||xy> = -conj(<xy||ma>) from the stored ooov class), and the energy
-// kernel forms the cyclic sums W~, Z~ and the two energy terms of each triple, reduced
-// in a fixed order.  The host sums the triples in order:
+// kernel forms the cyclic sums W~, Z~, Y~ and the three energy terms of each triple,
+// reduced in a fixed order.  The host sums the triples in order:
 // E = (1/6) sum_{i<j<k} sum_{abc} (the (1/36) sum over all ijk, abc).
-static void triples_impl(Handle& h, double* e4_out, double* e5_out) {
+static void triples_impl(Handle& h, double* e4_out, double* e5_out, double* ey_out) {
   if (h.phase32)
     raise(EXACC_ERR_INVALID_ARG,
           "triples need FP64 integrals: the handle is still in its low-precision phase");
   const int o = h.P.o, v = h.P.v;
   *e4_out = 0.0;
   *e5_out = 0.0;
+  *ey_out = 0.0;
   if (o < 3 || v < 3) return;
   const hipStream_t s = h.s;
   const int64_t vv = (int64_t)v * v, v3 = vv * v, ooo = (int64_t)o * o * o;
   const int nblk = triples_blocks(v);
   size_t free_b = 0, total_b = 0;
   HIPCHECK(hipMemGetInfo(&free_b, &total_b));
-  const size_t fixed = (size_t)(o * v3 + ooo + (int64_t)(o - 2) * nblk + 4) * 16 + (256u << 20);
+  const size_t fixed = (size_t)(o * v3 + 2 * ooo + 2 * (int64_t)(o - 2) * nblk + 4) * 16 + (256u << 20);
   if (fixed + (size_t)v3 * 16 > free_b)
     raise(EXACC_ERR_NOMEM, "triples: the <ab||ie> tiles (nocc * nvir^3 complex) do not fit in free device memory");
   // W rows (one per triple of a batch): what fits beside the tiles, at most o - 2
@@ -846,8 +847,8 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out) {
   h.use();
   double* Ve = h.dalloc(o * v3);
   double* W = h.dalloc(cap * v3);
-  double* part = h.dalloc(cap * nblk);
-  double* tri = h.dalloc(ooo);  // (e4, e5) at [i][j][k]
+  double* part = h.dalloc(2 * cap * nblk);  // 4 doubles per block
+  double* tri = h.dalloc(2 * ooo);           // (e4, e5, ey, -) at [i][j][k]
   struct Free {
     Handle& h;
     double** p[4];
@@ -896,21 +897,23 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out) {
         contract(s, "ima,mbc->iabc", MONE,
                  conj(sview(h.Vooov + 2 * ((int64_t)k * o + i0) * ov, {ni, o, v}, {ov, (int64_t)v, 1})),
                  Tone(j), true, Wv);
-        k_triples_energy(W, h.Voovv, h.x, h.eps, i0, ni, j, k, o, v, part, nblk, tri, s);
+        k_triples_energy(W, h.Voovv, T2, h.x, h.eps, i0, ni, j, k, o, v, part, nblk, tri, s);
       }
-  std::vector<double> host(2 * ooo);
+  std::vector<double> host(4 * ooo);
   HIPCHECK(hipMemcpyAsync(host.data(), tri, host.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
-  double e4 = 0, e5 = 0;
+  double e4 = 0, e5 = 0, ey = 0;
   for (int i = 0; i < o; ++i)
     for (int j = i + 1; j < o; ++j)
       for (int k = j + 1; k < o; ++k) {
         const int64_t q = ((int64_t)i * o + j) * o + k;
-        e4 += host[2 * q];
-        e5 += host[2 * q + 1];
+        e4 += host[4 * q];
+        e5 += host[4 * q + 1];
+        ey += host[4 * q + 2];
       }
   *e4_out = e4 / 6.0;
   *e5_out = (e4 + e5) / 6.0;
+  *ey_out = (e4 + ey) / 6.0;
 }
 
 // ------------------------------------------------------------------ create
@@ -1255,15 +1258,16 @@ int exacc_ccsd_residual(exacc_ccsd_t hh, double* s1, double* s2, int on_device) 
   });
 }
 
-int exacc_ccsd_triples(exacc_ccsd_t hh, double* e_plus_t, double* e_paren_t) {
+int exacc_ccsd_triples(exacc_ccsd_t hh, double* e_plus_t, double* e_paren_t, double* e_minus_t) {
   return guarded([&] {
     if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
     Handle& h = *reinterpret_cast<Handle*>(hh);
     h.use();
-    double e4 = 0, e5 = 0;
-    triples_impl(h, &e4, &e5);
+    double e4 = 0, e5 = 0, ey = 0;
+    triples_impl(h, &e4, &e5, &ey);
     if (e_plus_t) *e_plus_t = e4;
     if (e_paren_t) *e_paren_t = e5;
+    if (e_minus_t) *e_minus_t = ey;
     return (int)EXACC_OK;
   });
 }

@@ -65,7 +65,7 @@ def load():
     L.exacc_ccsd_get_amplitudes.argtypes = [P, P, P, I]
     L.exacc_ccsd_set_amplitudes.argtypes = [P, P, P, I]
     L.exacc_ccsd_residual.argtypes = [P, P, P, I]
-    L.exacc_ccsd_triples.argtypes = [P, dp, dp]
+    L.exacc_ccsd_triples.argtypes = [P, dp, dp, dp]
     L.exacc_ccsd_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p), dp, ip, I]
     L.exacc_ccsd_phase.argtypes = [P, ip, ip]
     L.exacc_ccsd_phase.restype = I
@@ -222,10 +222,10 @@ class CCSD:
         return r1, r2
 
     def triples(self):
-        """(E(+T), E((T))) at the current amplitudes (App. C), FP64, Hartree."""
-        e4, e5 = ctypes.c_double(0.0), ctypes.c_double(0.0)
-        _check(self.L.exacc_ccsd_triples(self.h, ctypes.byref(e4), ctypes.byref(e5)))
-        return e4.value, e5.value
+        """(E(+T), E((T)), E(-T)) at the current amplitudes (App. C), FP64, Hartree."""
+        e4, e5, ey = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+        _check(self.L.exacc_ccsd_triples(self.h, ctypes.byref(e4), ctypes.byref(e5), ctypes.byref(ey)))
+        return e4.value, e5.value, ey.value
 
     def phase(self):
         """(next step runs FP32 contractions, FP64 iterations since the switch)."""

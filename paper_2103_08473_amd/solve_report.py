@@ -72,10 +72,10 @@ def solve(eps_d, B_d, nocc, mode, tol, diis, max_iter, log, time_limit=None, tri
     tri = None
     if triples:
         t0 = time.perf_counter()
-        e4, et = cc.triples()
+        e4, et, em = cc.triples()
         dtt = time.perf_counter() - t0
         o, v, X = nocc, eps_d.numel() - nocc, B_d.shape[0]
-        tri = {"E(+T)": e4, "E((T))": et, "seconds": round(dtt, 3),
+        tri = {"E(+T)": e4, "E((T))": et, "E(-T)": em, "seconds": round(dtt, 3),
                "tflops": round(triples_flops(o, v, X) / dtt / 1e12, 3)}
         log("  triples %s" % json.dumps(tri))
     t1a, t2a = cc.amplitudes()
@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--save", default=None, help="keep E, t1 and a t2 sample of the first mode here")
     ap.add_argument("--ref", default=None, help="compare every mode with a solve kept by --save")
     ap.add_argument("--triples", action="store_true",
-                    help="after each solve, E(+T) and E((T)) (App. C) with their time")
+                    help="after each solve, E(+T), E((T)) and E(-T) (App. C) with their time")
     ap.add_argument("--time-limit", type=float, default=None,
                     help="stop iterating once this many seconds have passed since start-up")
     args = ap.parse_args()

@@ -143,8 +143,8 @@ def test_cc2_iterations_match_oracle(lib):
 
 @pytest.mark.parametrize("o,v,X", [(3, 3, 7), (5, 12, 30), (6, 17, 40), (8, 20, 50)])
 def test_triples_match_oracle(lib, o, v, X):
-    """E(+T), E((T)) (App. C) at random amplitudes vs the oracle (pinned by brute force):
-    1e-12 of |E(+T)|."""
+    """E(+T), E((T)), E(-T) (App. C) at random amplitudes vs the oracle (pinned by brute
+    force): 1e-12 of |E(+T)|."""
     from oracle.integrals import antisym
     from oracle.triples import triples_energies
     from paper_2103_08473_amd.exacc import CCSD
@@ -153,15 +153,16 @@ def test_triples_match_oracle(lib, o, v, X):
     t1, t2 = make_amplitudes(o, v, seed=3 + o, scale=0.1)
     n = o + v
     V = antisym(B, slice(0, n), slice(0, n), slice(0, n), slice(0, n))
-    e4, et = triples_energies(eps, V, o, t1, t2)
+    e4, et, em = triples_energies(eps, V, o, t1, t2)
     with CCSD(eps, B, o) as cc:
         cc.set_amplitudes(t1, t2)
-        g4, gt = cc.triples()
+        g4, gt, gm = cc.triples()
         r1, r2 = cc.amplitudes()
     assert np.array_equal(r1, t1) and np.array_equal(r2, t2)
-    assert abs(e4) > 1e-6
+    assert abs(e4) > 1e-6 and abs(et - e4) > 1e-9 and abs(em - e4) > 1e-9
     assert abs(g4 - e4) <= 1e-12 * abs(e4)
     assert abs(gt - et) <= 1e-12 * abs(e4)
+    assert abs(gm - em) <= 1e-12 * abs(e4)
 
 
 def test_ccsd_t_after_converged_solve(lib):
@@ -173,15 +174,15 @@ def test_ccsd_t_after_converged_solve(lib):
     eps, B = make_system(o, v, X, seed=17)
     ref = oracle.solve(eps, B, o, max_iter=80, tol=1e-11)
     n = o + v
-    e4, et = triples_energies(eps, antisym(B, slice(0, n), slice(0, n), slice(0, n), slice(0, n)),
-                              o, ref.t1, ref.t2)
+    e4, et, em = triples_energies(eps, antisym(B, slice(0, n), slice(0, n), slice(0, n), slice(0, n)),
+                                  o, ref.t1, ref.t2)
     with CCSD(eps, B, o, tol=1e-11, max_iter=80) as cc:
         e, conv, _ = cc.solve()
-        g4, gt = cc.triples()
+        g4, gt, gm = cc.triples()
     assert conv and ref.converged
     assert abs(e - ref.energy) <= 1e-10
-    assert abs(g4 - e4) <= 1e-10 and abs(gt - et) <= 1e-10
-    say("  CCSD %.10f  E(+T) %.3e  E((T)) %.3e" % (e.real, g4, gt))
+    assert abs(g4 - e4) <= 1e-10 and abs(gt - et) <= 1e-10 and abs(gm - em) <= 1e-10
+    say("  CCSD %.10f  E(+T) %.3e  E((T)) %.3e  E(-T) %.3e" % (e.real, g4, gt, gm))
 
 
 def test_one_electron_is_exact_at_first_step(lib):
@@ -226,6 +227,17 @@ def test_invalid_inputs_are_rejected(lib):
     with pytest.raises(exacc.ExaccError) as e:
         exacc.CCSD(eps, B, 4, hbm_budget_bytes=1 << 20)
     assert e.value.status == exacc.ERR_NOMEM
+    with pytest.raises(exacc.ExaccError) as e:      # CCD and CC2 are exclusive
+        exacc.CCSD(eps, B, 4, doubles_only=1, cc2=1)
+    assert e.value.status == exacc.ERR_INVALID_ARG
+    # triples need the FP64 integrals: refused while a mixed handle is still in FP32
+    with exacc.CCSD(eps, B, 4, precision=exacc.MIXED_FP32) as cc:
+        assert cc.phase()[0] == 1
+        with pytest.raises(exacc.ExaccError) as e:
+            cc.triples()
+        assert e.value.status == exacc.ERR_INVALID_ARG
+        st, _, r, _ = cc.iterate(1)                  # the handle stays usable
+        assert np.isfinite(r)
 
 
 def test_not_converged_status(lib):
