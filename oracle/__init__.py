@@ -20,7 +20,10 @@ Pins (tests/test_oracle_*.py, all CPU):
   * CCD (T1 = 0) for two electrons == CI over the reference and its doubles;
   * CC2 residuals == their defining second-quantised projections;
   * perturbative triples (oracle/triples.py): W~, Z~ == the connected and
-    disconnected triples projections, E(+T) == fourth-order triples energy.
+    disconnected triples projections, E(+T) == fourth-order triples energy;
+  * Lambda equations (oracle/cclambda.py) == the gradient of the CC Lagrangian
+    by brute force; the App. E density == the Lagrangian expectation value of
+    {q+ p}, == the exact 1-RDM for two electrons, diagonal == dE/d eps_p.
 """
 from .integrals import antisym, mulliken  # noqa: F401
 from .ccsd import (  # noqa: F401
@@ -29,3 +32,4 @@ from .ccsd import (  # noqa: F401
 )
 from .fci import fci_two_electron, fci_one_electron  # noqa: F401
 from .triples import triples_energies  # noqa: F401
+from .cclambda import density, lambda_residual, solve_lambda  # noqa: F401

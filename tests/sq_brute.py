@@ -132,3 +132,84 @@ def cc_residual(eps, V, nocc, t1, t2):
                     basis = F.ad(o + a, F.ad(o + b, aji))
                     S2[i, j, a, b] = np.vdot(basis, chi)
     return complex(np.vdot(phi0, chi) - e_ref), S1, S2
+
+
+# ---------------------------------------------------------------- CC Lagrangian
+def _tau_mu(F, o, mu, psi):
+    """tau_mu psi for mu = (i, a) (a+_a a_i) or (i, j, a, b) (a+_a a+_b a_j a_i)."""
+    if len(mu) == 2:
+        i, a = mu
+        return F.ad(o + a, F.a(i, psi))
+    i, j, a, b = mu
+    return F.ad(o + a, F.ad(o + b, F.a(j, F.a(i, psi))))
+
+
+def _excitations(o, v):
+    singles = [(i, a) for i in range(o) for a in range(v)]
+    doubles = [(i, j, a, b) for i in range(o) for j in range(i + 1, o)
+               for a in range(v) for b in range(a + 1, v)]
+    return singles, doubles
+
+
+def lagrangian_bra(F, o, l1, l2):
+    """The bra <0|(1 + Lambda) as a vector L with <L|psi> = L . psi (no conjugation):
+    <0| i+ a = <Phi_i^a| and <0| i+ j+ b a = <Phi_ij^ab|, with lambda as coefficients."""
+    v = l1.shape[1]
+    phi0 = np.zeros(1 << F.n, dtype=np.complex128)
+    phi0[(1 << o) - 1] = 1.0
+    L = phi0.copy()
+    singles, doubles = _excitations(o, v)
+    for mu in singles:
+        L += l1[mu] * _tau_mu(F, o, mu, phi0)
+    for mu in doubles:
+        L += l2[mu] * _tau_mu(F, o, mu, phi0)
+    return phi0, L
+
+
+def lagrangian_gradient(eps, V, nocc, t1, t2, l1, l2):
+    """dL/dt_mu = <0|(1+Lambda) e^-T [H, tau_mu] e^T|0> for every single and double
+    (L = <0|(1+Lambda) e^-T H e^T|0>, holomorphic in t), as (G1[i,a], G2[i,j,a,b])."""
+    n = eps.size
+    o = nocc
+    v = n - o
+    F = Fock(n)
+    h = core_h(eps, V, o)
+    phi0, L = lagrangian_bra(F, o, l1, l2)
+
+    def hbar(psi):
+        chi = exp_T(F, o, t1, t2, psi)
+        chi = apply_H(F, h, V, chi)
+        return exp_T(F, o, t1, t2, chi, sign=-1.0)
+
+    hb0 = hbar(phi0)
+    G1 = np.zeros((o, v), dtype=np.complex128)
+    G2 = np.zeros((o, o, v, v), dtype=np.complex128)
+    singles, doubles = _excitations(o, v)
+    for mu in singles + doubles:
+        val = np.dot(L, hbar(_tau_mu(F, o, mu, phi0))) - np.dot(L, _tau_mu(F, o, mu, hb0))
+        if len(mu) == 2:
+            G1[mu] = val
+        else:
+            i, j, a, b = mu
+            G2[i, j, a, b] = val
+            G2[j, i, a, b] = -val
+            G2[i, j, b, a] = -val
+            G2[j, i, b, a] = val
+    return G1, G2
+
+
+def lagrangian_density(nocc, t1, t2, l1, l2):
+    """gamma[p, q] = <0|(1+Lambda) e^-T {q+ p} e^T|0>: the element <q+ p>, minus the
+    reference's delta_pq for occupied p (normal order)."""
+    o, v = t1.shape
+    n = o + v
+    F = Fock(n)
+    phi0, L = lagrangian_bra(F, o, l1, l2)
+    chi = exp_T(F, o, t1, t2, phi0)
+    g = np.zeros((n, n), dtype=np.complex128)
+    for p in range(n):
+        ap = F.a(p, chi)
+        for q in range(n):
+            g[p, q] = np.dot(L, exp_T(F, o, t1, t2, F.ad(q, ap), sign=-1.0))
+    g[:o, :o] -= np.eye(o)
+    return g
