@@ -139,6 +139,46 @@ int exacc_ccsd_residual(exacc_ccsd_t h, double* s1, double* s2, int ptr_on_devic
  * nvir < 3.  The amplitudes and the iteration state are not changed. */
 int exacc_ccsd_triples(exacc_ccsd_t h, double* e_plus_t, double* e_paren_t, double* e_minus_t);
 
+/* Lambda (left-hand) equations of CCSD at the current amplitudes (App. D,
+ * working equations for the CCSD lambda equations), FP64: lambda solves
+ * dL/dt = 0 for the Lagrangian L = <0|(1 + Lambda) e^-T H e^T|0>.  Runs up to
+ * max_steps Jacobi + DIIS steps on lambda (the amplitude denominators and DIIS
+ * size; lambda starts at zero on the handle's first Lambda call); reports as
+ * exacc_ccsd_iterate, converged when ||Delta lambda||_2 <= opts.tol.  The
+ * amplitudes should be converged first; they are not changed.  The Lambda
+ * iteration and the amplitude iteration share the DIIS storage: switching
+ * from one to the other starts a fresh DIIS history.  Needs the FP64 phase and
+ * a CCSD handle (INVALID_ARG for CCD or CC2 handles, or while a mixed handle is
+ * in its low-precision phase).  The first call allocates the Lambda buffers
+ * (about 2 nocc^2 nvir^2 + nvir^2 naux + 3 nocc^3 nvir complex values; NOMEM if
+ * they do not fit); they stay with the handle until destroy. */
+int exacc_ccsd_lambda_iterate(exacc_ccsd_t h, int max_steps, int* steps_done,
+                              double* residual, int* converged);
+
+/* The Lambda residual at the current lambda, without updating it: r1
+ * [nocc][nvir], r2 [nocc][nocc][nvir][nvir] (full, antisymmetric), including
+ * the diagonal Fock part (r = D lambda + ..., D as for the amplitudes).
+ * Either may be NULL.  Same conditions as exacc_ccsd_lambda_iterate. */
+int exacc_ccsd_lambda_residual(exacc_ccsd_t h, double* r1, double* r2, int ptr_on_device);
+
+/* Copy lambda out / replace it, layouts as for the amplitudes: l1[i][a] =
+ * lambda_a^i, l2[i][j][a][b] = lambda_ab^ij (antisymmetric; set reads only the
+ * i<j, a<b entries; a NULL argument to set means zero).  Setting clears the
+ * Lambda DIIS history. */
+int exacc_ccsd_get_lambda(exacc_ccsd_t h, double* l1, double* l2, int ptr_on_device);
+int exacc_ccsd_set_lambda(exacc_ccsd_t h, const double* l1, const double* l2, int ptr_on_device);
+
+/* Correlation part of the one-body density of the CC Lagrangian at the
+ * current t and lambda (App. E, working equations for the Lagrange one-body
+ * density matrix): gamma [n][n] complex, gamma[p][q] =
+ * <0|(1 + Lambda) e^-T {q+ p} e^T|0>, blocks [i][j], [i][a] = lambda_a^i,
+ * [a][i], [a][b] with occupied spinors first.  The printed occupied block is
+ * the transpose of this element; the matrix is not symmetrised (its Hermitian
+ * part is the density used for properties).  Adding the identity on the
+ * occupied block gives the full density (trace = nocc).  Same conditions as
+ * exacc_ccsd_lambda_iterate. */
+int exacc_ccsd_density(exacc_ccsd_t h, double* gamma, int ptr_on_device);
+
 /* Accumulated device time in ms of each stage since create (or the last
  * reset), measured with HIP events on the handle's stream; requires
  * opts.timing = 1.  names[k] (static strings) and ms[k] for k < *count.

@@ -111,6 +111,12 @@ void k_triples_energy(const double* W, const double* Voovv, const double* T2, co
                       const double* eps, int i0, int ni, int j, int k, int o, int v, double* partial,
                       int nblk, double* out, hipStream_t s);
 // FP64 -> FP32, round to nearest even, nreal reals
+// dst[r][k] = conj(src[r * src_stride + k]) (complex elements)
+void k_conj_rows(double* dst, const double* src, int64_t rows, int64_t src_stride, int64_t len,
+                 hipStream_t s);
+// Lambda one-body density [n][n] from Go [o][o], M [o][o], l1 [o][v], Dvo [o][v], Gv [v][v], N [v][v]
+void k_lambda_density(const double* Go, const double* M, const double* l1, const double* Dvo,
+                      const double* Gv, const double* N, int o, int v, double* gamma, hipStream_t s);
 void k_cast(const double* in, float* out, int64_t nreal, hipStream_t s);
 int assemble_t2_blocks(int64_t npairs);
 void k_reduce_sum(const double* partial, int n, int width, double* out, hipStream_t s);

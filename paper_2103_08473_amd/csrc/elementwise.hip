@@ -474,6 +474,47 @@ __global__ void pack_amp_kernel(const double* __restrict__ t2, double* __restric
   }
 }
 
+// dst[r][k] = conj(src[r * src_stride + k]), k < len (complex elements)
+__global__ void conj_rows_kernel(double* __restrict__ dst, const double* __restrict__ src, int64_t rows,
+                                 int64_t src_stride, int64_t len) {
+  const int64_t tot = rows * len;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int64_t r = t / len, k = t - r * len;
+    z x = ld(src, r * src_stride + k);
+    x.y = -x.y;
+    st(dst, t, x);
+  }
+}
+
+// Lambda one-body density (App. E) from its pieces, gamma[p][q] = <{q+ p}>:
+//   oo [i][j] = -Go[j][i] - M[j][i]      (M[i][m] = sum_e l1[m][e] t1[i][e])
+//   ov [i][a] = l1[i][a]
+//   vo [a][i] = Dvo[i][a]
+//   vv [a][b] = -Gv[b][a] + N[a][b]      (N[a][b] = sum_m t1[m][a] l1[m][b])
+__global__ void lambda_density_kernel(const double* __restrict__ Go, const double* __restrict__ M,
+                                      const double* __restrict__ l1, const double* __restrict__ Dvo,
+                                      const double* __restrict__ Gv, const double* __restrict__ N,
+                                      int o, int v, double* __restrict__ g) {
+  const int n = o + v;
+  const int64_t tot = (int64_t)n * n;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int p = (int)(t / n), q = (int)(t - (int64_t)p * n);
+    z x;
+    if (p < o && q < o) {
+      const int64_t ji = (int64_t)q * o + p;
+      x = scal(-1.0, add(ld(Go, ji), ld(M, ji)));
+    } else if (p < o) {
+      x = ld(l1, (int64_t)p * v + (q - o));
+    } else if (q < o) {
+      x = ld(Dvo, (int64_t)q * v + (p - o));
+    } else {
+      const int a = p - o, b = q - o;
+      x = sub(ld(N, (int64_t)a * v + b), ld(Gv, (int64_t)b * v + a));
+    }
+    st(g, t, x);
+  }
+}
+
 __global__ void cast_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
   for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB)
     out[t] = (float)in[t];
@@ -482,6 +523,20 @@ __global__ void cast_kernel(const double* __restrict__ in, float* __restrict__ o
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+void k_conj_rows(double* dst, const double* src, int64_t rows, int64_t src_stride, int64_t len,
+                 hipStream_t s) {
+  const int64_t tot = rows * len;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(conj_rows_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, dst, src, rows, src_stride, len);
+  HIPCHECK(hipGetLastError());
+}
+void k_lambda_density(const double* Go, const double* M, const double* l1, const double* Dvo,
+                      const double* Gv, const double* N, int o, int v, double* gamma, hipStream_t s) {
+  const int64_t tot = (int64_t)(o + v) * (o + v);
+  hipLaunchKernelGGL(lambda_density_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, Go, M, l1, Dvo, Gv, N, o,
+                     v, gamma);
+  HIPCHECK(hipGetLastError());
+}
 void k_cast(const double* in, float* out, int64_t nreal, hipStream_t s) {
   if (nreal <= 0) return;
   hipLaunchKernelGGL(cast_kernel, dim3(nblocks(nreal)), dim3(TB), 0, s, in, out, nreal);

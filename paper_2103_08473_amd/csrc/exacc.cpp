@@ -158,6 +158,16 @@ struct Handle {
   int fp64_iters = 0;         // FP64 iterations since the last switch
   double best32 = -1.0;       // lowest ||Delta|| of the low-precision phase so far
   int since_best32 = 0;       // low-precision iterations since that lowest value
+  // Lambda equations (App. D): buffers allocated on first use.  prepared: the
+  // similarity-transformed Hamiltonian pieces (H4 = W_ovvo as [b][j][m][e], Cf = W_ovoo,
+  // Ap = W_oooo packed, Gac/Gki/Hkc = F_vv/-F_oo/F_ov, Wooov, the dressed factor Bd) were
+  // built from the current amplitudes and no other call has reused those buffers since.
+  struct Lam {
+    bool prepared = false;
+    double *lam = nullptr;   // [l1 (o v), l2 (i<j, a<b)], L complex
+    double *l1w, *Lq, *Z1, *Bd, *Wooov, *O3a, *O3b, *LTp, *Q1, *gP, *gt, *s1, *gam;
+  } lam;
+  int diis_owner = 0;         // 0: the amplitude DIIS history, 1: the Lambda one
   double* red = nullptr;      // reduction partials
   double* redout = nullptr;   // reduced values (device)
   double* host = nullptr;     // pinned readback
@@ -376,6 +386,55 @@ static void ensure_fp64_classes(Handle& h) {
 // Znp (packed) and Z (full) with no permutation left to apply, and R which
 // still needs P_ij P_ab (applied in the assembly), for the
 // amplitudes in h.x.
+// Particle-ladder product Znp[p][(a<b)] += sum_{c<d} Lp[p][(c<d)] (F_ac.F_bd - F_ad.F_bc), the
+// integrals formed tile by tile from factor rows F[a][c][P] (row a at F + a * row_stride,
+// [c][P] contiguous) and never stored whole: for each a, Ta[c][b][d] = sum_P F_ac F_bd over
+// b > a, antisymmetrised into W[(a,b)][(c<d)], then one GEMM per chunk of W rows.
+// bf: BF16x3 products; the pre-split rows h.Bvs (when present) are the factor B_vv itself
+// and may stand in for F only when use_bvs is set.
+template <typename R>
+static void ladder_apply(Handle& h, const Work<R>& w, const R* F, int64_t row_stride, const TV<R>& Lp,
+                         R* Znp, bool bf, bool use_bvs) {
+  const int v = h.P.v, X = h.P.X;
+  const int64_t Po = h.P.Po, Pv = h.P.Pv;
+  const hipStream_t s = h.s;
+  const int lad_build = bf ? GETT_LADDER_BUILD_BF16X3 : GETT_LADDER_BUILD;
+  const int lad_contract = bf ? GETT_LADDER_CONTRACT_BF16X3 : GETT_LADDER_CONTRACT;
+  if (Po == 0 || Pv == 0) return;
+  int64_t rows = 0, start = 0;
+  auto flush = [&]() {
+    if (rows == 0) return;
+    Scope sc(h, "ladder_contract");
+    auto Wv = view(w.W, {rows, Pv});
+    auto Zc = sview(Znp + 2 * start, {Po, rows}, {Pv, 1});
+    contract(s, "py,xy->px", ONE, Lp, Wv, true, Zc, lad_contract);
+    start += rows;
+    rows = 0;
+  };
+  for (int a = 0; a + 1 < v; ++a) {
+    const int nb = v - a - 1;
+    if (rows + nb > h.P.chunk_pairs) flush();
+    {
+      Scope sc(h, "ladder_build");
+      if (bf && use_bvs && h.Bvs) {  // Ta[c][b][d] = sum_P B[(a,c)][P] B[(b,d)][P], b > a, pre-split rows
+        const int64_t rs = 4 * (int64_t)bf16x3_split_k(X);
+        gemm_bf16x3_split(h.Bvs + (int64_t)a * v * rs, h.Bvs + (int64_t)(a + 1) * v * rs, v, nb * v, X,
+                          reinterpret_cast<float*>(w.Ta), (int64_t)nb * v, s);
+      } else {
+        auto Ba = sview(const_cast<R*>(F) + 2 * (int64_t)a * row_stride, {v, X}, {X, 1});
+        auto Bb = sview(const_cast<R*>(F) + 2 * (int64_t)(a + 1) * row_stride, {nb, v, X}, {row_stride, X, 1});
+        contract(s, "cP,bdP->cbd", ONE, Ba, Bb, false, view(w.Ta, {v, nb, v}), lad_build);
+      }
+    }
+    {
+      Scope sc(h, "ladder_antisym");
+      k_ladder_antisym<R>(w.Ta, w.W + 2 * rows * Pv, nb, v, s);
+    }
+    rows += nb;
+  }
+  flush();
+}
+
 template <typename R>
 static void compute_residual(Handle& h) {
   Work<R> w = work<R>(h);
@@ -539,43 +598,7 @@ static void compute_residual(Handle& h) {
   }
   // particle ladder: Znp[ij][ab] += sum_{c<d} tau[ij][cd] <ab||cd>, <ab||cd> = (ac|bd) - (ad|bc)
   // (BF16x3 products in the low-precision phase of the BF16x3 mode)
-  const int lad_build = bf ? GETT_LADDER_BUILD_BF16X3 : GETT_LADDER_BUILD;
-  const int lad_contract = bf ? GETT_LADDER_CONTRACT_BF16X3 : GETT_LADDER_CONTRACT;
-  if (Po > 0 && Pv > 0) {
-    const int64_t nX = (int64_t)h.P.n * X;
-    int64_t rows = 0, start = 0;
-    auto flush = [&]() {
-      if (rows == 0) return;
-      Scope sc(h, "ladder_contract");
-      auto Wv = view(w.W, {rows, Pv});
-      auto Zc = sview(w.Znp + 2 * start, {Po, rows}, {Pv, 1});
-      contract(s, "py,xy->px", ONE, taup, Wv, true, Zc, lad_contract);
-      start += rows;
-      rows = 0;
-    };
-    for (int a = 0; a + 1 < v; ++a) {
-      const int nb = v - a - 1;
-      if (rows + nb > h.P.chunk_pairs) flush();
-      {
-        Scope sc(h, "ladder_build");
-        if (bf && h.Bvs) {  // Ta[c][b][d] = sum_P B[(a,c)][P] B[(b,d)][P], b > a, pre-split rows
-          const int64_t rs = 4 * (int64_t)bf16x3_split_k(X);
-          gemm_bf16x3_split(h.Bvs + (int64_t)a * v * rs, h.Bvs + (int64_t)(a + 1) * v * rs, v, nb * v,
-                            X, reinterpret_cast<float*>(w.Ta), (int64_t)nb * v, s);
-        } else {
-          auto Ba = sview(b.Bvv.p + 2 * (int64_t)a * nX, {v, X}, {X, 1});
-          auto Bb = sview(b.Bvv.p + 2 * (int64_t)(a + 1) * nX, {nb, v, X}, {nX, X, 1});
-          contract(s, "cP,bdP->cbd", ONE, Ba, Bb, false, view(w.Ta, {v, nb, v}), lad_build);
-        }
-      }
-      {
-        Scope sc(h, "ladder_antisym");
-        k_ladder_antisym<R>(w.Ta, w.W + 2 * rows * Pv, nb, v, s);
-      }
-      rows += nb;
-    }
-    flush();
-  }
+  ladder_apply<R>(h, w, b.Bvv.p, (int64_t)h.P.n * X, taup, w.Znp, bf, true);
   if (ccd)
     dzero(h, w.S1, (int64_t)o * v);
   else
@@ -709,27 +732,14 @@ static zc device_energy(Handle& h) {
   return zc(h.host[0], h.host[1]);
 }
 
-static double one_iteration(Handle& h) {
-  const int o = h.P.o, v = h.P.v;
-  const int64_t ov = (int64_t)o * v, L = h.P.L;
-  const bool was32 = h.phase32;
-  compute_residual_phase(h);
-  // pick the DIIS slot (drop the oldest pair when full)
+// The assembly wrote (x + e, e) into DIIS slot `slot` and the squared step norm into
+// redout[0]: add the Gram row of e against the stored error vectors, drop the oldest
+// pairs while the subspace is ill-conditioned, solve for the coefficients and write the
+// extrapolated vector to target.  Returns ||e||.
+static double diis_commit(Handle& h, int slot, double* target) {
+  const int64_t L = h.P.L;
   const int cap = h.P.nslots;
-  if ((int)h.order.size() == cap) {
-    h.order.erase(h.order.begin());
-  }
-  int slot = 0;
-  for (; slot < cap; ++slot)
-    if (std::find(h.order.begin(), h.order.end(), slot) == h.order.end()) break;
-  double* xt = h.slot_x(slot);
-  double* e = h.slot_e(slot);
-  {
-    Scope sc(h, "assemble");
-    const int nb = was32 ? assemble<float>(h, xt, e, nullptr, nullptr, h.op.level_shift)
-                         : assemble<double>(h, xt, e, nullptr, nullptr, h.op.level_shift);
-    k_reduce_sum(h.red, nb + 1, 1, h.redout, h.s);
-  }
+  const double* e = h.slot_e(slot);
   // Gram row of the new error vector against every stored one (and itself)
   std::vector<int> ids = h.order;
   ids.push_back(slot);
@@ -777,8 +787,34 @@ static double one_iteration(Handle& h) {
       xs.push_back(h.slot_x(h.order[k]));
       cc.push_back(cplx{c[k].real(), c[k].imag()});
     }
-    k_lincomb(h.x, xs.data(), cc.data(), (int)xs.size(), L, h.s);
+    k_lincomb(target, xs.data(), cc.data(), (int)xs.size(), L, h.s);
   }
+  return rnorm;
+}
+
+// Pick the DIIS slot for the next pair (drop the oldest pair when full).
+static int diis_slot(Handle& h) {
+  const int cap = h.P.nslots;
+  if ((int)h.order.size() == cap) h.order.erase(h.order.begin());
+  int slot = 0;
+  for (; slot < cap; ++slot)
+    if (std::find(h.order.begin(), h.order.end(), slot) == h.order.end()) break;
+  return slot;
+}
+
+static double one_iteration(Handle& h) {
+  const bool was32 = h.phase32;
+  compute_residual_phase(h);
+  const int slot = diis_slot(h);
+  double* xt = h.slot_x(slot);
+  double* e = h.slot_e(slot);
+  {
+    Scope sc(h, "assemble");
+    const int nb = was32 ? assemble<float>(h, xt, e, nullptr, nullptr, h.op.level_shift)
+                         : assemble<double>(h, xt, e, nullptr, nullptr, h.op.level_shift);
+    k_reduce_sum(h.red, nb + 1, 1, h.redout, h.s);
+  }
+  const double rnorm = diis_commit(h, slot, h.x);
   h.energy = device_energy(h);
   timer_collect(h);
   h.iters++;
@@ -917,6 +953,324 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out, double* ey_o
 }
 
 // ------------------------------------------------------------------ create
+// ------------------------------------------------------------------ Lambda equations
+// App. D: the left-hand (Lambda) equations at converged amplitudes, FP64.  The
+// intermediates are the one- and two-body elements of e^-T H e^T, built once per
+// amplitude set (lambda_prepare); each Lambda iteration then forms R1, R2 from them,
+// with the expensive pieces taken through the DF factors instead of stored whole:
+//   * the particle ladder 1/2 sum_ef l_ij^ef W_efab, with W_efab = sum_P (Bd_ae Bd_bf -
+//     Bd_af Bd_be) + 1/2 sum_mn t_mn^ef <mn||ab> and the T1-dressed factor
+//     Bd[a][e][P] = B^P_ea - sum_m t_m^e B^P_ma: the amplitude ladder's tile builder run
+//     on Bd, plus two packed o^4 v^2 GEMMs;
+//   * 1/2 sum_mef l_im^ef W_efam (the vvvo element) term by term: <ef||am> through
+//     (ea|fm), the W_vvvv part as t1 times the ladder product above, and the t2 part
+//     through the ring-shaped Z1[i][n][f][g] = sum_me l_im^ef t_nm^eg;
+//   * the vovv element through its definition <ej||ab> - sum_n t_n^e <nj||ab>.
+// The diagonal Fock part of R is left to the assembly (D times lambda), as for the
+// amplitudes, so F_vv and F_oo here exclude it.
+static void lambda_invalidate(Handle& h) { h.lam.prepared = false; }
+
+static void lambda_alloc(Handle& h) {
+  if (h.lam.lam) return;
+  const int64_t o = h.P.o, v = h.P.v, X = h.P.X;
+  const int64_t need = h.P.L + 3 * o * v + 2 * h.P.oovv + v * v * X + 3 * o * o * o * v +
+                       h.P.Po * h.P.Po + o * o * X + X + (o + v) * (o + v);
+  size_t fr = 0, tot = 0;
+  HIPCHECK(hipMemGetInfo(&fr, &tot));
+  if ((size_t)need * 16 + (256u << 20) > fr) raise(EXACC_ERR_NOMEM, "Lambda buffers do not fit");
+  Handle::Lam& L = h.lam;
+  L.lam = h.dalloc(h.P.L);
+  L.l1w = h.dalloc(o * v);
+  L.s1 = h.dalloc(o * v);
+  L.gt = h.dalloc(o * v);
+  L.Lq = h.dalloc(h.P.oovv);
+  L.Z1 = h.dalloc(h.P.oovv);
+  L.Bd = h.dalloc(v * v * X);
+  L.Wooov = h.dalloc(o * o * o * v);
+  L.O3a = h.dalloc(o * o * o * v);
+  L.O3b = h.dalloc(o * o * o * v);
+  L.LTp = h.dalloc(h.P.Po * h.P.Po);
+  L.Q1 = h.dalloc(o * o * X);
+  L.gP = h.dalloc(X);
+  L.gam = h.dalloc((o + v) * (o + v));
+  dzero(h, L.lam, h.P.L);
+}
+
+static void lambda_check(Handle& h) {
+  if (h.phase32)
+    raise(EXACC_ERR_INVALID_ARG, "Lambda equations need the FP64 integrals: iterate into the FP64 phase first");
+  if (h.op.doubles_only || h.op.cc2)
+    raise(EXACC_ERR_INVALID_ARG, "Lambda equations are those of CCSD; not for CCD or CC2 handles");
+  h.use();
+  lambda_alloc(h);
+}
+
+static void lambda_prepare(Handle& h) {
+  if (h.lam.prepared) return;
+  Work<double> w = work<double>(h);
+  const int o = h.P.o, v = h.P.v, X = h.P.X, n = h.P.n;
+  const int64_t Po = h.P.Po, ov = (int64_t)o * v, oov = (int64_t)o * o * v;
+  const hipStream_t s = h.s;
+  Views<double> b = bviews(h, w.Bt);
+  Handle::Lam& L = h.lam;
+  const double* t1p = h.x;
+  const double* t2p = h.x + 2 * ov;
+  Scope sc(h, "lambda_prepare");
+  dcopy(h, h.t1w, h.x, ov);
+  auto t1 = view(h.t1w, {o, v});
+  k_unpack_tau<double>(t1p, t2p, w.Z, w.TAU, w.taup, o, v, s);
+  k_ring_operands<double>(w.Z, t1p, w.Tq, w.Xp, o, v, s);
+  auto T2 = sview(w.Tq, {o, o, v, v}, {ov, v, 1, oov});
+  auto TAU = view(w.TAU, {o, o, v, v});
+  auto Voovv = view(w.Voovv, {o, o, v, v});
+  auto Vooov = view(w.Vooov, {o, o, o, v});
+  // one-body: Gac = F_vv, Gki = -F_oo (both without the diagonal Fock part), Hkc = F_ov
+  auto Hac = view(w.Hac, {v, v}), Gac = view(w.Gac, {v, v});
+  auto Hki = view(w.Hki, {o, o}), Gki = view(w.Gki, {o, o});
+  auto Hkc = view(w.Hkc, {o, v});
+  contract(s, "klcd,klda->ac", HALF, Voovv, TAU, false, Hac);
+  contract(s, "klcd,licd->ki", HALF, Voovv, TAU, false, Hki);
+  dcopy(h, w.Gac, w.Hac, (int64_t)v * v);
+  dcopy(h, w.Gki, w.Hki, (int64_t)o * o);
+  contract(s, "klcd,ld->kc", ONE, Voovv, t1, false, Hkc);
+  auto y = view(w.y, {X});
+  auto U = view(w.U, {o, o, X});
+  auto Vt = view(w.Vt, {v, o, X});
+  contract(s, "kdP,kd->P", ONE, b.Bov, t1, false, y);
+  contract(s, "kdP,id->kiP", ONE, b.Bov, t1, false, U);
+  contract(s, "acP,ic->aiP", ONE, b.Bvv, t1, false, Vt);
+  contract(s, "acP,P->ac", ONE, b.Bvv, y, true, Gac);
+  contract(s, "akP,kcP->ac", MONE, Vt, b.Bov, true, Gac);
+  contract(s, "klic,lc->ki", MONE, Vooov, t1, true, Gki);
+  // W_oooo [m][n][i][j] in Af, packed over both pairs into Ap[(mn)][(ij)]
+  auto Af = view(w.Af, {o, o, o, o});
+  dcopy(h, w.Af, w.Voooo, (int64_t)o * o * o * o);
+  contract(s, "klic,jc->klij", ONE, Vooov, t1, true, Af);
+  contract(s, "kljc,ic->klij", MONE, Vooov, t1, true, Af);
+  contract(s, "klcd,ijcd->klij", HALF, Voovv, TAU, true, Af);
+  if (Po > 0) k_pack_last2<double>(w.Ap, w.Af, h.rowmap_o, Po, o, (int64_t)o * o, s);
+  // W_ooov [m][n][i][e] = <mn||ie> + sum_f t_i^f <mn||fe>
+  auto Wooov = view(L.Wooov, {o, o, o, v});
+  dcopy(h, L.Wooov, w.Vooov, (int64_t)o * o * o * v);
+  contract(s, "if,mnfe->mnie", ONE, t1, Voovv, true, Wooov);
+  // W_ovvo as Wq[b][j][m][e] = W_ovvo[j][e][b][m] = -H'[e][m][j][b], H'[a][i][k][c] the ring
+  // intermediate of the amplitude equations with the full t2 in place of t2/2
+  auto Wq = sview(w.H4, {v, o, o, v}, {1, v, ov, oov});
+  contract(s, "acP,kiP->aikc", MONE, b.Bvv, b.Boo, false, Wq);
+  contract(s, "aiP,kcP->aikc", ONE, b.Bvo, b.Bov, true, Wq);
+  contract(s, "acP,kiP->aikc", MONE, b.Bvv, U, true, Wq);
+  contract(s, "aiP,kcP->aikc", ONE, Vt, b.Bov, true, Wq);
+  contract(s, "klic,la->aikc", ONE, Vooov, t1, true, Wq);
+  contract(s, "aild,klcd->aikc", MONE, view(w.Xp, {v, o, o, v}), Voovv, true, Wq);
+  contract(s, "aild,klcd->aikc", cplx{-0.5, 0}, view(w.Tq, {v, o, o, v}), Voovv, true, Wq);
+  // W_ovoo as Cf[i][j][b][m] = W_ovoo[m][b][i][j]
+  const int64_t vo = (int64_t)v * o;
+  auto Cp = view(w.Cp, {Po, v, o});
+  auto taup = view(w.taup, {Po, h.P.Pv});
+  if (Po > 0) contract(s, "bkx,px->pbk", MONE, view(w.Vvovv_p, {v, o, h.P.Pv}), taup, false, Cp);
+  k_expand_c<double>(w.Vooov, w.Cp, w.Cf, o, v, s);
+  auto Cf = view(w.Cf, {o, o, v, o});
+  auto Cfji = sview(w.Cf, {o, o, v, o}, {vo, o * vo, o, 1});
+  contract(s, "me,ijbe->ijbm", MONE, Hkc, T2, true, Cf);
+  contract(s, "nb,mnij->ijbm", MONE, t1, Af, true, Cf);
+  contract(s, "mnie,jnbe->ijbm", ONE, Vooov, T2, true, Cf);
+  contract(s, "mnie,jnbe->ijbm", MONE, Vooov, T2, true, Cfji);
+  contract(s, "miP,bjP->ijbm", ONE, U, b.Bvo, true, Cf);
+  contract(s, "mjP,biP->ijbm", MONE, b.Boo, Vt, true, Cf);
+  contract(s, "miP,bjP->ijbm", MONE, U, b.Bvo, true, Cfji);
+  contract(s, "mjP,biP->ijbm", ONE, b.Boo, Vt, true, Cfji);
+  auto Wt = view(L.O3a, {o, o, o, v});
+  contract(s, "ie,mnef->mnif", ONE, t1, Voovv, false, Wt);
+  contract(s, "mnif,njbf->ijbm", MONE, Wt, T2, true, Cf);
+  contract(s, "mnif,njbf->ijbm", ONE, Wt, T2, true, Cfji);
+  // dressed factor Bd[a][e][P] = B^P_ea - sum_m t_m^e B^P_ma (B^P_qp = conj(B^P_pq))
+  k_conj_rows(L.Bd, b.Bvv.p, v, (int64_t)n * X, (int64_t)v * X, s);
+  contract(s, "amP,me->aeP", MONE, conj(b.Bvo), t1, true, view(L.Bd, {v, v, X}));
+  L.prepared = true;
+}
+
+// R1 into S1 and the pieces of R2 into Z (no permutation), R (P_ij P_ab at assembly)
+// and Znp (packed), at the Lambda amplitudes in h.lam.lam.
+static void lambda_compute(Handle& h) {
+  lambda_prepare(h);
+  Work<double> w = work<double>(h);
+  const int o = h.P.o, v = h.P.v, X = h.P.X;
+  const int64_t Po = h.P.Po, Pv = h.P.Pv, ov = (int64_t)o * v, oov = (int64_t)o * o * v;
+  const int64_t vv = (int64_t)v * v, ovv = (int64_t)o * v * v;
+  const hipStream_t s = h.s;
+  Views<double> b = bviews(h, w.Bt);
+  Handle::Lam& L = h.lam;
+  Scope sc(h, "lambda_residual");
+  const double* l2p = L.lam + 2 * ov;
+  dcopy(h, L.l1w, L.lam, ov);
+  k_unpack_full(nullptr, l2p, nullptr, w.Z, o, v, s);
+  k_ring_operands<double>(w.Z, h.x, L.Lq, w.Xp, o, v, s);  // Lq[b][i][k][a] = l_ik^ab
+  auto l1 = view(L.l1w, {o, v});
+  auto t1 = view(h.t1w, {o, v});
+  auto L2 = sview(L.Lq, {o, o, v, v}, {ov, v, 1, oov});
+  auto T2 = sview(w.Tq, {o, o, v, v}, {ov, v, 1, oov});
+  auto Voovv = view(w.Voovv, {o, o, v, v});
+  auto Vooov = view(w.Vooov, {o, o, o, v});
+  auto Gac = view(w.Gac, {v, v}), Gki = view(w.Gki, {o, o}), Hkc = view(w.Hkc, {o, v});
+  auto Wooov = view(L.Wooov, {o, o, o, v});
+  auto Wq = view(w.H4, {v, o, o, v});
+  // G^e_a and G^i_m of App. D: Gv[a][e] = -1/2 sum t_mn^ef l_mn^af, Go[m][i] = 1/2 sum t_mn^ef l_in^ef
+  auto Gv = view(w.Hac, {v, v}), Go = view(w.Hki, {o, o});
+  contract(s, "mnef,mnaf->ae", cplx{-0.5, 0}, T2, L2, false, Gv);
+  contract(s, "mnef,inef->mi", HALF, T2, L2, false, Go);
+
+  // ---- R2, pieces without a permutation operator (Z and its swapped views)
+  auto Z = view(w.Z, {o, o, v, v});
+  auto Zji = sview(w.Z, {o, o, v, v}, {vv, ovv, v, 1});
+  auto Zba = sview(w.Z, {o, o, v, v}, {ovv, vv, 1, v});
+  dcopy(h, w.Z, w.Voovv, h.P.oovv);  // <ij||ab>
+  contract(s, "ijae,eb->ijab", ONE, L2, Gac, true, Z);
+  contract(s, "ijae,eb->ijab", MONE, L2, Gac, true, Zba);
+  contract(s, "imab,jm->ijab", ONE, L2, Gki, true, Z);
+  contract(s, "imab,jm->ijab", MONE, L2, Gki, true, Zji);
+  auto M1 = view(w.M1, {o, o});
+  contract(s, "ie,ne->in", ONE, l1, t1, false, M1);
+  contract(s, "in,njab->ijab", MONE, M1, Voovv, true, Z);
+  contract(s, "in,njab->ijab", ONE, M1, Voovv, true, Zji);
+  contract(s, "ma,ijmb->ijab", MONE, l1, Wooov, true, Z);
+  contract(s, "ma,ijmb->ijab", ONE, l1, Wooov, true, Zba);
+  contract(s, "ijae,be->ijab", ONE, Voovv, Gv, true, Z);
+  contract(s, "ijae,be->ijab", MONE, Voovv, Gv, true, Zba);
+  contract(s, "imab,mj->ijab", MONE, Voovv, Go, true, Z);
+  contract(s, "imab,mj->ijab", ONE, Voovv, Go, true, Zji);
+  // ---- R2, pieces under P_ij P_ab (R)
+  auto Rv = view(w.R_, {o, o, v, v});
+  contract(s, "aime,bjme->ijab", MONE, view(L.Lq, {v, o, o, v}), Wq, false, Rv, GETT_RING);
+  auto Yv = view(w.Y, {o, v, X});
+  contract(s, "ie,aeP->iaP", ONE, l1, conj(b.Bvv), false, Yv);
+  contract(s, "iaP,jbP->ijab", ONE, Yv, b.Bov, true, Rv);
+  contract(s, "iaz,jbz->ijab", ONE, sview(L.l1w, {o, v, 1}, {v, 1, 1}), sview(w.Hkc, {o, v, 1}, {v, 1, 1}),
+           true, Rv);
+  // ---- R2, packed pieces (Znp): first the W_vvvv ladder alone, which R1 also needs
+  auto Znp = view(w.Znp, {Po, Pv});
+  auto l2v = view(const_cast<double*>(l2p), {Po, Pv});
+  if (Po > 0 && Pv > 0) {
+    auto LT = view(L.LTp, {Po, Po});
+    contract(s, "py,qy->pq", ONE, l2v, view(h.x + 2 * ov, {Po, Pv}), false, LT);
+    contract(s, "pq,qx->px", ONE, LT, view(h.Voovv_p, {Po, Pv}), false, Znp);
+    ladder_apply<double>(h, w, L.Bd, (int64_t)v * X, l2v, w.Znp, false, false);
+  }
+  // ---- R1
+  auto S1 = view(w.S1, {o, v});
+  dcopy(h, w.S1, w.Hkc, ov);
+  if (Po > 0 && Pv > 0) {  // sum_mg t_m^g (1/2 sum_ef l_im^ef W_efag)
+    k_unpack_full(nullptr, w.Znp, nullptr, L.Z1, o, v, s);
+    contract(s, "imag,mg->ia", ONE, view(L.Z1, {o, o, v, v}), t1, true, S1);
+    contract(s, "pq,qx->px", ONE, view(w.Ap, {Po, Po}), l2v, true, Znp);  // 1/2 l_mn^ab W_ijmn
+  }
+  contract(s, "ie,ea->ia", ONE, l1, Gac, true, S1);
+  contract(s, "ma,im->ia", ONE, l1, Gki, true, S1);
+  contract(s, "me,aime->ia", ONE, l1, Wq, true, S1);
+  // 1/2 sum l_im^ef <ef||am> = sum_mef l_im^ef (ea|fm)
+  contract(s, "imef,fmP->ieP", ONE, L2, b.Bvo, false, Yv);
+  contract(s, "ieP,aeP->ia", ONE, Yv, conj(b.Bvv), true, S1);
+  contract(s, "ni,na->ia", MONE, Go, Hkc, true, S1);
+  // 1/4 sum_{mno} (sum_ef l_im^ef tau_no^ef) <no||am>
+  auto LTo = view(w.Af, {o, o, o, o});
+  contract(s, "imef,noef->imno", ONE, L2, view(w.TAU, {o, o, v, v}), false, LTo);
+  contract(s, "imno,noma->ia", cplx{-0.25, 0}, LTo, Vooov, true, S1);
+  // - sum_{nfg} Z1[i][n][f][g] <nf||ag>, Z1 = sum_me l_im^ef t_nm^eg
+  auto Z1 = view(L.Z1, {o, o, v, v});
+  contract(s, "fime,gnme->infg", ONE, view(L.Lq, {v, o, o, v}), view(w.Tq, {v, o, o, v}), false, Z1,
+           GETT_RING);
+  auto Q1 = view(L.Q1, {o, o, X});
+  contract(s, "infg,fgP->inP", ONE, Z1, b.Bvv, false, Q1);
+  contract(s, "inP,naP->ia", MONE, Q1, b.Bov, true, S1);
+  contract(s, "infg,ngP->ifP", ONE, Z1, b.Bov, false, Yv);
+  contract(s, "ifP,faP->ia", ONE, Yv, b.Bvv, true, S1);
+  // - sum Lt[i][m][n][f] (<nf||am> - sum_og t_om^fg <no||ag>), Lt = sum_e l_im^ef t_n^e
+  auto Lt = view(L.O3a, {o, o, o, v});
+  contract(s, "imef,ne->imnf", ONE, L2, t1, false, Lt);
+  contract(s, "imnf,fmP->inP", ONE, Lt, b.Bvo, false, Q1);
+  contract(s, "inP,naP->ia", MONE, Q1, b.Bov, true, S1);
+  contract(s, "imnf,nmP->ifP", ONE, Lt, b.Boo, false, Yv);
+  contract(s, "ifP,faP->ia", ONE, Yv, b.Bvv, true, S1);
+  auto M2 = view(L.O3b, {o, o, o, v});
+  contract(s, "imnf,omfg->inog", ONE, Lt, T2, false, M2);
+  contract(s, "inog,noag->ia", ONE, M2, Voovv, true, S1);
+  // - 1/2 sum l_mn^ae W_iemn (W_ovoo in Cf[m][n][e][i])
+  contract(s, "mnae,mnei->ia", cplx{-0.5, 0}, L2, view(w.Cf, {o, o, v, o}), true, S1);
+  // - sum_ef G_ef W_eifa, W_eifa = <ei||fa> - sum_n t_n^e <ni||fa>
+  auto gP = view(L.gP, {X});
+  contract(s, "efP,ef->P", ONE, b.Bvv, Gv, false, gP);
+  contract(s, "iaP,P->ia", MONE, b.Bov, gP, true, S1);
+  contract(s, "ef,ifP->ieP", ONE, Gv, b.Bov, false, Yv);
+  contract(s, "ieP,aeP->ia", ONE, Yv, conj(b.Bvv), true, S1);
+  auto gt = view(L.gt, {o, v});
+  contract(s, "ef,ne->nf", ONE, Gv, t1, false, gt);
+  contract(s, "nf,nifa->ia", ONE, gt, Voovv, true, S1);
+  contract(s, "mn,mina->ia", MONE, Go, Wooov, true, S1);
+}
+
+// Assembly of R + D lambda: the Jacobi step into (xt, e), or the full residual into (s1, s2).
+static int lambda_assemble(Handle& h, double* xt, double* e, double* s1, double* s2) {
+  Work<double> w = work<double>(h);
+  const int o = h.P.o, v = h.P.v;
+  const int64_t ov = (int64_t)o * v, np = h.P.Po * h.P.Pv;
+  k_assemble_t1<double>(w.S1, h.lam.lam, h.eps, o, v, 0.0, 0, xt, e, s1, s1 ? nullptr : h.red, h.s);
+  int nb = 0;
+  if (np > 0) {
+    nb = assemble_t2_blocks(np);
+    k_assemble_t2<double>(w.Znp, w.Z, w.R_, nullptr, h.lam.lam + 2 * ov, h.eps, o, v, 0.0,
+                          xt ? xt + 2 * ov : nullptr, e ? e + 2 * ov : nullptr, s2,
+                          s2 ? nullptr : h.red + 1, nb, h.s);
+  }
+  return nb;
+}
+
+static double lambda_iteration(Handle& h) {
+  if (h.diis_owner != 1) {
+    reset_diis(h);
+    h.diis_owner = 1;
+  }
+  lambda_compute(h);
+  const int slot = diis_slot(h);
+  {
+    Scope sc(h, "assemble");
+    const int nb = lambda_assemble(h, h.slot_x(slot), h.slot_e(slot), nullptr, nullptr);
+    k_reduce_sum(h.red, nb + 1, 1, h.redout, h.s);
+  }
+  const double r = diis_commit(h, slot, h.lam.lam);
+  timer_collect(h);
+  return r;
+}
+
+// The one-body density of App. E at the current t and lambda into gamma_dev [n][n].
+static void lambda_density(Handle& h, double* gamma_dev) {
+  lambda_prepare(h);
+  Work<double> w = work<double>(h);
+  const int o = h.P.o, v = h.P.v;
+  const int64_t ov = (int64_t)o * v, oov = (int64_t)o * o * v;
+  const hipStream_t s = h.s;
+  Handle::Lam& L = h.lam;
+  dcopy(h, L.l1w, L.lam, ov);
+  k_unpack_full(nullptr, L.lam + 2 * ov, nullptr, w.Z, o, v, s);
+  k_ring_operands<double>(w.Z, h.x, L.Lq, w.Xp, o, v, s);
+  auto l1 = view(L.l1w, {o, v});
+  auto t1 = view(h.t1w, {o, v});
+  auto L2 = sview(L.Lq, {o, o, v, v}, {ov, v, 1, oov});
+  auto T2 = sview(w.Tq, {o, o, v, v}, {ov, v, 1, oov});
+  auto Gv = view(w.Hac, {v, v}), Go = view(w.Hki, {o, o});
+  contract(s, "mnef,mnaf->ae", cplx{-0.5, 0}, T2, L2, false, Gv);
+  contract(s, "mnef,inef->mi", HALF, T2, L2, false, Go);
+  auto M = view(w.M1, {o, o});
+  contract(s, "me,ie->im", ONE, l1, t1, false, M);
+  auto Dvo = view(L.gt, {o, v});
+  dcopy(h, L.gt, h.t1w, ov);
+  contract(s, "me,imae->ia", ONE, l1, T2, true, Dvo);
+  contract(s, "im,ma->ia", MONE, M, t1, true, Dvo);
+  contract(s, "im,ma->ia", MONE, Go, t1, true, Dvo);
+  contract(s, "ie,ea->ia", ONE, t1, Gv, true, Dvo);
+  auto N = view(L.Z1, {v, v});
+  contract(s, "ma,mb->ab", ONE, t1, l1, false, N);
+  k_lambda_density(w.Hki, w.M1, L.l1w, L.gt, w.Hac, L.Z1, o, v, gamma_dev, s);
+}
+
 static void validate_host_inputs(int o, int v, const double* eps) {
   double emax = -1e300, emin = 1e300;
   for (int i = 0; i < o + v; ++i)
@@ -1164,6 +1518,11 @@ int exacc_ccsd_iterate(exacc_ccsd_t hh, int max_steps, int* steps_done, double* 
     if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
     Handle& h = *reinterpret_cast<Handle*>(hh);
     h.use();
+    lambda_invalidate(h);
+    if (h.diis_owner != 0) {
+      reset_diis(h);
+      h.diis_owner = 0;
+    }
     for (int k = 0; k < max_steps; ++k) {
       const double r = one_iteration(h);
       if (steps_done) *steps_done = k + 1;
@@ -1200,6 +1559,7 @@ int exacc_ccsd_get_amplitudes(exacc_ccsd_t hh, double* t1, double* t2, int on_de
     if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
     Handle& h = *reinterpret_cast<Handle*>(hh);
     h.use();
+    lambda_invalidate(h);
     const int o = h.P.o, v = h.P.v;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (t1) HIPCHECK(hipMemcpyAsync(t1, h.x, (size_t)o * v * 16, k, h.s));
@@ -1217,6 +1577,7 @@ int exacc_ccsd_set_amplitudes(exacc_ccsd_t hh, const double* t1, const double* t
     if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
     Handle& h = *reinterpret_cast<Handle*>(hh);
     h.use();
+    lambda_invalidate(h);
     const int o = h.P.o, v = h.P.v;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if (t1)
@@ -1240,6 +1601,7 @@ int exacc_ccsd_residual(exacc_ccsd_t hh, double* s1, double* s2, int on_device) 
     if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
     Handle& h = *reinterpret_cast<Handle*>(hh);
     h.use();
+    lambda_invalidate(h);
     const int o = h.P.o, v = h.P.v;
     compute_residual_phase(h);
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -1263,11 +1625,111 @@ int exacc_ccsd_triples(exacc_ccsd_t hh, double* e_plus_t, double* e_paren_t, dou
     if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
     Handle& h = *reinterpret_cast<Handle*>(hh);
     h.use();
+    lambda_invalidate(h);
     double e4 = 0, e5 = 0, ey = 0;
     triples_impl(h, &e4, &e5, &ey);
     if (e_plus_t) *e_plus_t = e4;
     if (e_paren_t) *e_paren_t = e5;
     if (e_minus_t) *e_minus_t = ey;
+    return (int)EXACC_OK;
+  });
+}
+
+int exacc_ccsd_lambda_iterate(exacc_ccsd_t hh, int max_steps, int* steps_done, double* residual,
+                              int* converged) {
+  if (steps_done) *steps_done = 0;
+  if (converged) *converged = 0;
+  return guarded([&] {
+    if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    lambda_check(h);
+    double first = -1.0;
+    for (int k = 0; k < max_steps; ++k) {
+      const double r = lambda_iteration(h);
+      if (steps_done) *steps_done = k + 1;
+      if (residual) *residual = r;
+      if (first < 0) first = r;
+      if (!std::isfinite(r) || r > 1e6 * std::max(first, 1e-300)) return (int)EXACC_ERR_DIVERGED;
+      if (r <= h.op.tol) {
+        if (converged) *converged = 1;
+        return (int)EXACC_OK;
+      }
+    }
+    return (int)EXACC_NOT_CONVERGED;
+  });
+}
+
+int exacc_ccsd_lambda_residual(exacc_ccsd_t hh, double* r1, double* r2, int on_device) {
+  return guarded([&] {
+    if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    lambda_check(h);
+    const int o = h.P.o, v = h.P.v;
+    lambda_compute(h);
+    // full residual into Z1 and R1 into the s1 buffer, both unused by the assembly
+    dzero(h, h.lam.Z1, h.P.oovv);
+    lambda_assemble(h, nullptr, nullptr, h.lam.s1, h.lam.Z1);
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (r1) HIPCHECK(hipMemcpyAsync(r1, h.lam.s1, (size_t)o * v * 16, k, h.s));
+    if (r2) HIPCHECK(hipMemcpyAsync(r2, h.lam.Z1, (size_t)h.P.oovv * 16, k, h.s));
+    HIPCHECK(hipStreamSynchronize(h.s));
+    timer_collect(h);
+    return (int)EXACC_OK;
+  });
+}
+
+int exacc_ccsd_get_lambda(exacc_ccsd_t hh, double* l1, double* l2, int on_device) {
+  return guarded([&] {
+    if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    lambda_check(h);
+    const int o = h.P.o, v = h.P.v;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (l1) HIPCHECK(hipMemcpyAsync(l1, h.lam.lam, (size_t)o * v * 16, k, h.s));
+    if (l2) {
+      k_unpack_full(nullptr, h.lam.lam + 2 * (int64_t)o * v, nullptr, h.lam.Z1, o, v, h.s);
+      HIPCHECK(hipMemcpyAsync(l2, h.lam.Z1, (size_t)h.P.oovv * 16, k, h.s));
+    }
+    HIPCHECK(hipStreamSynchronize(h.s));
+    return (int)EXACC_OK;
+  });
+}
+
+int exacc_ccsd_set_lambda(exacc_ccsd_t hh, const double* l1, const double* l2, int on_device) {
+  return guarded([&] {
+    if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    lambda_check(h);
+    const int o = h.P.o, v = h.P.v;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (l1)
+      HIPCHECK(hipMemcpyAsync(h.lam.lam, l1, (size_t)o * v * 16, k, h.s));
+    else
+      dzero(h, h.lam.lam, (int64_t)o * v);
+    if (l2) {
+      HIPCHECK(hipMemcpyAsync(h.lam.Z1, l2, (size_t)h.P.oovv * 16, k, h.s));
+      k_pack_amplitudes(nullptr, h.lam.Z1, h.lam.lam + 2 * (int64_t)o * v, o, v, h.s);
+    } else {
+      dzero(h, h.lam.lam + 2 * (int64_t)o * v, h.P.Po * h.P.Pv);
+    }
+    HIPCHECK(hipStreamSynchronize(h.s));
+    if (h.diis_owner == 1) reset_diis(h);
+    return (int)EXACC_OK;
+  });
+}
+
+int exacc_ccsd_density(exacc_ccsd_t hh, double* gamma, int on_device) {
+  return guarded([&] {
+    if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
+    if (!gamma) raise(EXACC_ERR_INVALID_ARG, "null output");
+    Handle& h = *reinterpret_cast<Handle*>(hh);
+    lambda_check(h);
+    const int64_t n = h.P.n;
+    double* g = on_device ? gamma : h.lam.gam;
+    lambda_density(h, g);
+    if (!on_device) HIPCHECK(hipMemcpyAsync(gamma, g, (size_t)n * n * 16, hipMemcpyDeviceToHost, h.s));
+    HIPCHECK(hipStreamSynchronize(h.s));
+    timer_collect(h);
     return (int)EXACC_OK;
   });
 }

@@ -66,6 +66,11 @@ def load():
     L.exacc_ccsd_set_amplitudes.argtypes = [P, P, P, I]
     L.exacc_ccsd_residual.argtypes = [P, P, P, I]
     L.exacc_ccsd_triples.argtypes = [P, dp, dp, dp]
+    L.exacc_ccsd_lambda_iterate.argtypes = [P, I, ip, dp, ip]
+    L.exacc_ccsd_lambda_residual.argtypes = [P, P, P, I]
+    L.exacc_ccsd_get_lambda.argtypes = [P, P, P, I]
+    L.exacc_ccsd_set_lambda.argtypes = [P, P, P, I]
+    L.exacc_ccsd_density.argtypes = [P, P, I]
     L.exacc_ccsd_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p), dp, ip, I]
     L.exacc_ccsd_phase.argtypes = [P, ip, ip]
     L.exacc_ccsd_phase.restype = I
@@ -78,7 +83,9 @@ def load():
     L.exacc_last_error.restype = ctypes.c_char_p
     for f in ("exacc_ccsd_create", "exacc_ccsd_iterate", "exacc_ccsd_energy",
               "exacc_ccsd_get_amplitudes", "exacc_ccsd_set_amplitudes", "exacc_ccsd_residual",
-              "exacc_ccsd_triples", "exacc_ccsd_stage_times", "exacc_ccsd_destroy"):
+              "exacc_ccsd_triples", "exacc_ccsd_lambda_iterate", "exacc_ccsd_lambda_residual",
+              "exacc_ccsd_get_lambda", "exacc_ccsd_set_lambda", "exacc_ccsd_density",
+              "exacc_ccsd_stage_times", "exacc_ccsd_destroy"):
         getattr(L, f).restype = I
     _lib = L
     return L
@@ -226,6 +233,57 @@ class CCSD:
         e4, e5, ey = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_double(0.0)
         _check(self.L.exacc_ccsd_triples(self.h, ctypes.byref(e4), ctypes.byref(e5), ctypes.byref(ey)))
         return e4.value, e5.value, ey.value
+
+    # ---- Lambda equations (App. D) and the one-body density (App. E)
+    def lambda_iterate(self, max_steps=1):
+        """Lambda steps at the current amplitudes; returns (status, steps_done, residual,
+        converged)."""
+        steps, conv = ctypes.c_int(), ctypes.c_int()
+        res = ctypes.c_double()
+        st = self.L.exacc_ccsd_lambda_iterate(self.h, max_steps, ctypes.byref(steps),
+                                              ctypes.byref(res), ctypes.byref(conv))
+        _check(st, allow=(OK, NOT_CONVERGED, ERR_DIVERGED))
+        return st, steps.value, res.value, bool(conv.value)
+
+    def lambda_solve(self, max_iter=None):
+        """Iterate the Lambda equations until converged; returns (converged, history of
+        ||Delta lambda||)."""
+        max_iter = self.opts.max_iter if max_iter is None else max_iter
+        hist = []
+        conv = False
+        for _ in range(max_iter):
+            st, _, r, conv = self.lambda_iterate(1)
+            hist.append(r)
+            if st == ERR_DIVERGED or conv:
+                break
+        return conv, hist
+
+    def lambda_residual(self):
+        """R1 [o,v], R2 [o,o,v,v] of the Lambda equations at the current lambda."""
+        o, v = self.nocc, self.nvir
+        r1 = np.zeros((o, v), np.complex128)
+        r2 = np.zeros((o, o, v, v), np.complex128)
+        _check(self.L.exacc_ccsd_lambda_residual(self.h, r1.ctypes.data, r2.ctypes.data, 0))
+        return r1, r2
+
+    def get_lambda(self):
+        o, v = self.nocc, self.nvir
+        l1 = np.zeros((o, v), np.complex128)
+        l2 = np.zeros((o, o, v, v), np.complex128)
+        _check(self.L.exacc_ccsd_get_lambda(self.h, l1.ctypes.data, l2.ctypes.data, 0))
+        return l1, l2
+
+    def set_lambda(self, l1, l2):
+        a, pa = _host_c128(l1)
+        b, pb = _host_c128(l2)
+        _check(self.L.exacc_ccsd_set_lambda(self.h, pa, pb, 0))
+
+    def density(self):
+        """Correlation one-body density gamma[p, q] = <{q+ p}> [n, n] (App. E)."""
+        n = self.nocc + self.nvir
+        g = np.zeros((n, n), np.complex128)
+        _check(self.L.exacc_ccsd_density(self.h, g.ctypes.data, 0))
+        return g
 
     def phase(self):
         """(next step runs FP32 contractions, FP64 iterations since the switch)."""

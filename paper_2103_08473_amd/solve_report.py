@@ -45,7 +45,8 @@ def triples_flops(o, v, X):
     return 8.0 * (2.0 * o * v ** 3 * X + ntrip * (3.0 * v ** 4 + 3.0 * o * v ** 3))
 
 
-def solve(eps_d, B_d, nocc, mode, tol, diis, max_iter, log, time_limit=None, triples=False, **extra):
+def solve(eps_d, B_d, nocc, mode, tol, diis, max_iter, log, time_limit=None, triples=False,
+          lam=False, **extra):
     import torch
     t0 = time.perf_counter()
     cc = exacc.CCSD(eps_d, B_d, nocc, precision=MODES[mode], tol=tol, diis_size=diis,
@@ -78,6 +79,31 @@ def solve(eps_d, B_d, nocc, mode, tol, diis, max_iter, log, time_limit=None, tri
         tri = {"E(+T)": e4, "E((T))": et, "E(-T)": em, "seconds": round(dtt, 3),
                "tflops": round(triples_flops(o, v, X) / dtt / 1e12, 3)}
         log("  triples %s" % json.dumps(tri))
+    lres = None
+    if lam:
+        t0 = time.perf_counter()
+        lhist = []
+        lconv = False
+        for _ in range(max_iter):
+            ti = time.perf_counter()
+            st, _, r, lconv = cc.lambda_iterate(1)
+            lhist.append((r, time.perf_counter() - ti))
+            log("  lambda it %3d |D| %.3e  t %.1fs" % (len(lhist), r, time.perf_counter() - t0))
+            if lconv or st == exacc.ERR_DIVERGED:
+                break
+        dtl = time.perf_counter() - t0
+        g = cc.density()
+        n = g.shape[0]
+        herm = 0.5 * (g + g.conj().T)
+        lres = {"converged": lconv, "iterations": len(lhist), "seconds": round(dtl, 3),
+                "first_iteration_s": round(lhist[0][1], 3) if lhist else None,
+                "s_per_iter_after_first": round(float(np.mean([x[1] for x in lhist[1:]])), 4)
+                if len(lhist) > 1 else None,
+                "residual": lhist[-1][0] if lhist else None,
+                "density_trace": [float(np.trace(g).real), float(np.trace(g).imag)],
+                "density_hermitian_part_max_offdiag": float(np.abs(herm - np.diag(np.diag(herm))).max())
+                if n > 1 else 0.0}
+        log("  lambda %s" % json.dumps(lres))
     t1a, t2a = cc.amplitudes()
     cc.close()
     low_t = [h[5] for h in hist if h[1] == "low"]
@@ -88,7 +114,7 @@ def solve(eps_d, B_d, nocc, mode, tol, diis, max_iter, log, time_limit=None, tri
             "s_per_low_iter": round(float(np.mean(low_t)), 4) if low_t else None,
             "s_per_fp64_iter": round(float(np.mean(hi_t)), 4) if hi_t else None,
             "residual": hist[-1][4] if hist else None,
-            "triples": tri, "history": hist}, t1a, t2a
+            "triples": tri, "lambda": lres, "history": hist}, t1a, t2a
 
 
 def random_unique_t2(o, v, n, seed=SAMPLE_SEED):
@@ -142,6 +168,8 @@ def main():
     ap.add_argument("--ref", default=None, help="compare every mode with a solve kept by --save")
     ap.add_argument("--triples", action="store_true",
                     help="after each solve, E(+T), E((T)) and E(-T) (App. C) with their time")
+    ap.add_argument("--lambda", dest="lam", action="store_true",
+                    help="after each solve, the Lambda equations (App. D) and the density (App. E)")
     ap.add_argument("--time-limit", type=float, default=None,
                     help="stop iterating once this many seconds have passed since start-up")
     args = ap.parse_args()
@@ -164,7 +192,7 @@ def main():
         log("solve %s" % mode)
         extra = {} if args.switch_tol is None else {"mixed_switch_tol": args.switch_tol}
         res, t1, t2 = solve(eps_d, B_d, o, mode, args.tol, args.diis, args.max_iter, log,
-                            time_limit=args.time_limit, triples=args.triples, **extra)
+                            time_limit=args.time_limit, triples=args.triples, lam=args.lam, **extra)
         if args.ref:
             res.update(compare_saved(args.ref, res, t1, t2, o, v))
         if args.save and not out["modes"]:
