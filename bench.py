@@ -154,6 +154,22 @@ def main():
     dt = time.perf_counter() - t0
     stages = cc.stage_times(reset=True)
     E = cc.energy()
+    # Lambda equations (App. D) on the same handle, at these amplitudes: the first step
+    # also builds the transformed-Hamiltonian pieces, so it is the warm-up
+    lam = {}
+    if not args.no_mixed:
+        cc.lambda_iterate(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            cc.lambda_iterate(1)
+        torch.cuda.synchronize()
+        dtl = (time.perf_counter() - t0) / args.steps
+        sl = cc.stage_times(reset=True)
+        lam = {"lambda_fp64": {
+            "s_per_iter": round(dtl, 4),
+            "ccsd_iteration_time_ratio": round((dt / args.steps) / dtl, 3),
+            "stage_ms_per_iter": {k: round(t / (args.steps + 1), 2) for k, t in sl.items()}}}
     cc.close()
 
     # CCD (the paper's CCDOUBLES) and CC2 variants: same system, FP64
@@ -247,6 +263,7 @@ def main():
                      "hw_frac": round(0.75 * achieved / PEAK_FP64_MFMA, 4),
                      "counters": measured_mfma_busy()},
     }
+    out.update(lam)
     out.update(ccd)
     out.update(mixed)
     if not args.no_cpu_baseline:
