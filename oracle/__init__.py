@@ -23,7 +23,9 @@ Pins (tests/test_oracle_*.py, all CPU):
     disconnected triples projections, E(+T) == fourth-order triples energy;
   * Lambda equations (oracle/cclambda.py) == the gradient of the CC Lagrangian
     by brute force; the App. E density == the Lagrangian expectation value of
-    {q+ p}, == the exact 1-RDM for two electrons, diagonal == dE/d eps_p.
+    {q+ p}, == the exact 1-RDM for two electrons, diagonal == dE/d eps_p;
+  * DF factors (oracle/dffactors.py): fitted integrals == their closed form for
+    J = L K, V = L L^T, and == the linear-solve route.
 """
 from .integrals import antisym, mulliken  # noqa: F401
 from .ccsd import (  # noqa: F401
@@ -33,3 +35,4 @@ from .ccsd import (  # noqa: F401
 from .fci import fci_two_electron, fci_one_electron  # noqa: F401
 from .triples import triples_energies  # noqa: F401
 from .cclambda import density, lambda_residual, solve_lambda  # noqa: F401
+from .dffactors import df_factors, metric_inverse_sqrt  # noqa: F401

@@ -94,3 +94,27 @@ def serving_request(k: int):
     r = float(rng.uniform(5.0, 9.0))
     nvir = int(round(r * nocc))
     return nocc, nvir, 3 * nvir, 1000 + k
+
+
+def make_df_inputs(nao: int, nspinor: int, naux: int, seed: int = 0, sigma: float = 0.1):
+    """Inputs of DF-factor generation: AO three-index integrals J[Q][mu][nu] (complex,
+    Hermitian in mu nu), the fitting metric V[Q][R] (real, symmetric positive definite)
+    and orthonormal spinor coefficients C[mu][p] (complex, nspinor <= nao).
+
+    J and V come from an underlying factorisation: K[P][mu][nu] ~ N(0, sigma^2)
+    (Hermitian), L = I + (strictly lower, N(0, (0.3 / sqrt(naux))^2)), J = L K
+    (J[Q] = sum_P L[Q][P] K[P]) and V = L L^T, so that J V^-1 J = K K exactly (the
+    fitted integrals have a known closed form).  C: the first nspinor columns of the
+    unitary factor of a complex Gaussian matrix.  Returns (C, J, V, K)."""
+    if nspinor > nao:
+        raise ValueError("nspinor > nao")
+    rng = np.random.default_rng(seed)
+    K = rng.normal(0.0, sigma, (naux, nao, nao)) + 1j * rng.normal(0.0, sigma, (naux, nao, nao))
+    K = 0.5 * (K + np.conj(K.transpose(0, 2, 1)))
+    L = np.eye(naux) + np.tril(rng.normal(0.0, 0.3 / math.sqrt(naux), (naux, naux)), -1)
+    J = np.einsum("QP,Pmn->Qmn", L, K)
+    V = L @ L.T
+    G = rng.normal(size=(nao, nao)) + 1j * rng.normal(size=(nao, nao))
+    Q, _ = np.linalg.qr(G)
+    C = np.ascontiguousarray(Q[:, :nspinor])
+    return C, np.ascontiguousarray(J), np.ascontiguousarray(V), K
