@@ -179,6 +179,30 @@ int exacc_ccsd_set_lambda(exacc_ccsd_t h, const double* l1, const double* l2, in
  * exacc_ccsd_lambda_iterate. */
 int exacc_ccsd_density(exacc_ccsd_t h, double* gamma, int ptr_on_device);
 
+/* Density-fitting factors from AO three-index integrals (the step before the
+ * CC iteration; the paper's Introduction names density fitting for the
+ * integral tensor, its Performance section the cost of the AO->MO
+ * transformation): with (mu nu|Q) = J[Q][mu][nu] (complex [naux][nao][nao]),
+ * the fitting metric V[Q][R] = (Q|R) (real symmetric positive definite
+ * [naux][naux]) and spinor coefficients C[mu][p] (complex [nao][nspinor]),
+ *   B[P][p][q] = sum_Q [V^-1/2]_PQ sum_{mu nu} conj(C[mu][p]) J[Q][mu][nu] C[nu][q]
+ * (complex [naux][nspinor][nspinor]; Hermitian in pq when J is Hermitian in
+ * mu nu), so that sum_P B[P][p][q] B[P][r][s] is the fitted (pq|rs): the input
+ * of exacc_ccsd_create.  V^-1/2 comes from the coupled Newton-Schulz iteration
+ * (matrix products only) on V scaled by its largest absolute row sum;
+ * *ns_iterations (may be NULL) receives its step count.  Pointers are device
+ * pointers (ptrs_on_device = 1) or host pointers (0); the caller owns them.
+ * stream: hipStream_t or NULL (the call then uses a stream of its own).
+ * Temporary device memory of 6 naux^2 + naux nspinor (nao + nspinor) complex
+ * values (plus copies of the inputs for host pointers) is allocated and freed
+ * inside the call (NOMEM if it does not fit).  INVALID_ARG for sizes outside
+ * 1 <= nspinor <= nao, naux >= 1, null pointers, or a metric on which the
+ * iteration does not converge (not positive definite, or condition number
+ * beyond about 1e14). */
+int exacc_df_factors(int nao, int nspinor, int naux, const double* C, const double* J,
+                     const double* V, double* B, int ptrs_on_device, void* stream,
+                     int* ns_iterations);
+
 /* Accumulated device time in ms of each stage since create (or the last
  * reset), measured with HIP events on the handle's stream; requires
  * opts.timing = 1.  names[k] (static strings) and ms[k] for k < *count.

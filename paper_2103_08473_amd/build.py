@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libexacc.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["gett.hip", "elementwise.hip", "einsum.cpp", "exacc.cpp"]
+SOURCES = ["gett.hip", "elementwise.hip", "einsum.cpp", "exacc.cpp", "dffactors.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

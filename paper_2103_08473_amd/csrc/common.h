@@ -111,6 +111,10 @@ void k_triples_energy(const double* W, const double* Voovv, const double* T2, co
                       const double* eps, int i0, int ni, int j, int k, int o, int v, double* partial,
                       int nblk, double* out, hipStream_t s);
 // FP64 -> FP32, round to nearest even, nreal reals
+// DF factors B[X][n][n] from C [m][n], J [X][m][m] (complex) and the real metric V [X][X]
+// (all device pointers when on_device, else host); returns the Newton-Schulz step count
+int df_factors_impl(int m, int n, int X, const double* C, const double* J, const double* V, double* B,
+                    bool on_device, hipStream_t s);
 // dst[r][k] = conj(src[r * src_stride + k]) (complex elements)
 void k_conj_rows(double* dst, const double* src, int64_t rows, int64_t src_stride, int64_t len,
                  hipStream_t s);

@@ -1734,6 +1734,34 @@ int exacc_ccsd_density(exacc_ccsd_t hh, double* gamma, int on_device) {
   });
 }
 
+int exacc_df_factors(int nao, int nspinor, int naux, const double* C, const double* J, const double* V,
+                     double* B, int ptrs_on_device, void* stream, int* ns_iterations) {
+  return guarded([&] {
+    if (nao < 1 || nspinor < 1 || naux < 1 || nspinor > nao)
+      raise(EXACC_ERR_INVALID_ARG, "DF factors: need 1 <= nspinor <= nao and naux >= 1");
+    if (!C || !J || !V || !B) raise(EXACC_ERR_INVALID_ARG, "DF factors: null pointer");
+    if ((int64_t)naux * nao * nao > 0x7fffffffLL || (int64_t)naux * nspinor * nspinor > 0x7fffffffLL ||
+        (int64_t)naux * naux > 0x7fffffffLL)
+      raise(EXACC_ERR_INVALID_ARG, "DF factors: extent beyond 2^31");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    bool own = false;
+    if (!s) {
+      HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      own = true;
+    }
+    struct StreamGuard {
+      hipStream_t s;
+      bool own;
+      ~StreamGuard() {
+        if (own) (void)hipStreamDestroy(s);
+      }
+    } sg{s, own};
+    const int it = df_factors_impl(nao, nspinor, naux, C, J, V, B, ptrs_on_device != 0, s);
+    if (ns_iterations) *ns_iterations = it;
+    return (int)EXACC_OK;
+  });
+}
+
 int exacc_ccsd_stage_times(exacc_ccsd_t hh, const char** names, double* ms, int* count, int reset) {
   return guarded([&] {
     if (!hh || !count) raise(EXACC_ERR_INVALID_ARG, "null argument");

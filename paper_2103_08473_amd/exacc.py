@@ -71,6 +71,7 @@ def load():
     L.exacc_ccsd_get_lambda.argtypes = [P, P, P, I]
     L.exacc_ccsd_set_lambda.argtypes = [P, P, P, I]
     L.exacc_ccsd_density.argtypes = [P, P, I]
+    L.exacc_df_factors.argtypes = [I, I, I, P, P, P, P, I, P, ip]
     L.exacc_ccsd_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p), dp, ip, I]
     L.exacc_ccsd_phase.argtypes = [P, ip, ip]
     L.exacc_ccsd_phase.restype = I
@@ -85,6 +86,7 @@ def load():
               "exacc_ccsd_get_amplitudes", "exacc_ccsd_set_amplitudes", "exacc_ccsd_residual",
               "exacc_ccsd_triples", "exacc_ccsd_lambda_iterate", "exacc_ccsd_lambda_residual",
               "exacc_ccsd_get_lambda", "exacc_ccsd_set_lambda", "exacc_ccsd_density",
+              "exacc_df_factors",
               "exacc_ccsd_stage_times", "exacc_ccsd_destroy"):
         getattr(L, f).restype = I
     _lib = L
@@ -126,6 +128,31 @@ def memory_estimate(nocc, nvir, naux, **kw):
 
 def ladder_flops(nocc, nvir, naux):
     return float(load().exacc_ladder_flops(nocc, nvir, naux))
+
+
+def df_factors(C, J, V, stream=None):
+    """DF factors B[P][p][q] from spinor coefficients C [nao][n], AO three-index integrals
+    J [naux][nao][nao] and the metric V [naux][naux] (exacc_df_factors).  numpy inputs give
+    a numpy result (host pointers); torch CUDA tensors (complex128 C, J; float64 V) give a
+    torch CUDA tensor.  Returns (B, Newton-Schulz step count)."""
+    L = load()
+    it = ctypes.c_int(0)
+    if _is_torch(C):
+        import torch
+        nao, n = C.shape
+        X = J.shape[0]
+        B = torch.empty((X, n, n), dtype=torch.complex128, device=C.device)
+        _check(L.exacc_df_factors(nao, n, X, C.data_ptr(), J.data_ptr(), V.data_ptr(), B.data_ptr(),
+                                  1, stream, ctypes.byref(it)))
+        return B, it.value
+    c, pc = _host_c128(C)
+    j, pj = _host_c128(J)
+    v = np.ascontiguousarray(V, dtype=np.float64)
+    nao, n = c.shape
+    X = j.shape[0]
+    B = np.zeros((X, n, n), np.complex128)
+    _check(L.exacc_df_factors(nao, n, X, pc, pj, v.ctypes.data, B.ctypes.data, 0, None, ctypes.byref(it)))
+    return B, it.value
 
 
 def _is_torch(x):
