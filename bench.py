@@ -189,6 +189,38 @@ def main():
             ccd[name] = {"s_per_iter": round(dtc, 4),
                          "ccsd_iteration_time_ratio": round((dt / args.steps) / dtc, 3)}
 
+    # DF-factor generation (the step before the iteration) for the same spinor count:
+    # nao = 600 AO functions, nspinor = o + v = 400, naux = X.  Inputs made on the device
+    # with torch (J = L K, V = L L^T, orthonormal C); not part of the timed product.
+    dfleg = {}
+    if not args.no_mixed:
+        try:
+            g = torch.Generator(device="cuda").manual_seed(5)
+            nao, nsp = 600, o + v
+            K = torch.randn((X, nao, nao), dtype=torch.complex128, device="cuda", generator=g) * 0.05
+            K = 0.5 * (K + K.transpose(1, 2).conj())
+            Lm = torch.eye(X, dtype=torch.float64, device="cuda") + torch.tril(
+                torch.randn((X, X), dtype=torch.float64, device="cuda", generator=g), -1) * (0.3 / X ** 0.5)
+            J = (Lm.to(torch.complex128) @ K.reshape(X, -1)).reshape(X, nao, nao).contiguous()
+            del K
+            Vm = (Lm @ Lm.T).contiguous()
+            Cq = torch.linalg.qr(torch.randn((nao, nao), dtype=torch.complex128, device="cuda",
+                                             generator=g))[0][:, :nsp].contiguous()
+            exacc.df_factors(Cq, J, Vm)                      # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Bdf, nsit = exacc.df_factors(Cq, J, Vm)
+            torch.cuda.synchronize()
+            dtd = time.perf_counter() - t0
+            fl = 8.0 * (X * nsp * nao * nao + X * nsp * nsp * nao + X * X * nsp * nsp + nsit * 3.0 * X ** 3)
+            dfleg = {"df_factors": {"nao": nao, "nspinor": nsp, "naux": X, "seconds": round(dtd, 4),
+                                    "newton_schulz_steps": nsit, "tflops": round(fl / dtd / 1e12, 3),
+                                    "flops_counted": "complex GEMM work, 8 flops per multiply-add"}}
+            del J, Vm, Cq, Bdf, Lm
+            torch.cuda.empty_cache()
+        except Exception as ex:  # the headline line must still print
+            dfleg = {"df_factors": {"error": str(ex)[:200]}}
+
     mixed = {}
     if not args.no_mixed:
         # same system, low-precision phases of the mixed schedules
@@ -264,6 +296,7 @@ def main():
                      "counters": measured_mfma_busy()},
     }
     out.update(lam)
+    out.update(dfleg)
     out.update(ccd)
     out.update(mixed)
     if not args.no_cpu_baseline:
