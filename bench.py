@@ -141,6 +141,10 @@ def main():
     eps_d = torch.from_numpy(eps).cuda()
     B_d = torch.from_numpy(B).cuda()
     stream = torch.cuda.Stream()
+    def progress(msg):
+        print("bench: " + msg, file=sys.stderr, flush=True)
+
+    progress("fp64 CCSD iterations")
     cc = exacc.CCSD(eps_d, B_d, o, stream=stream.cuda_stream, timing=1, tol=1e-9)
     for _ in range(args.warmup):
         cc.iterate(1)
@@ -158,6 +162,7 @@ def main():
     # also builds the transformed-Hamiltonian pieces, so it is the warm-up
     lam = {}
     if not args.no_mixed:
+        progress("lambda iterations")
         cc.lambda_iterate(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -176,6 +181,7 @@ def main():
     ccd = {}
     if not args.no_mixed:
         for name, kw in (("ccd_fp64", {"doubles_only": 1}), ("cc2_fp64", {"cc2": 1})):
+            progress(name)
             cd = exacc.CCSD(eps_d, B_d, o, stream=stream.cuda_stream, timing=1, tol=1e-9, **kw)
             for _ in range(args.warmup):
                 cd.iterate(1)
@@ -195,6 +201,7 @@ def main():
     dfleg = {}
     if not args.no_mixed:
         try:
+            progress("df factors")
             g = torch.Generator(device="cuda").manual_seed(5)
             nao, nsp = 600, o + v
             K = torch.randn((X, nao, nao), dtype=torch.complex128, device="cuda", generator=g) * 0.05
@@ -225,6 +232,7 @@ def main():
     if not args.no_mixed:
         # same system, low-precision phases of the mixed schedules
         for name, prec in (("mixed_fp32", exacc.MIXED_FP32), ("mixed_bf16x3", exacc.MIXED_BF16X3)):
+            progress(name)
             cm = exacc.CCSD(eps_d, B_d, o, stream=stream.cuda_stream, timing=1, tol=1e-9,
                             precision=prec)
             for _ in range(args.warmup):
@@ -300,6 +308,7 @@ def main():
     out.update(ccd)
     out.update(mixed)
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(eps, B, o)
     print(json.dumps(out), flush=True)
 
