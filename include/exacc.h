@@ -72,6 +72,9 @@ typedef struct {
                                 default 0 = CCSD */
   int    cc2;                /* .CC2: 1 = CC2 (T1 equation unchanged; doubles from the T1-dressed
                                 <ab||ij> plus the diagonal Fock term); exclusive with doubles_only */
+  int    triples_occ_block;  /* perturbative triples: occupied block size n_red of the three nested
+                                block loops (<ab||ie> tiles of three blocks resident); 0 = the
+                                largest that fits in free device memory (all of nocc if possible) */
 } exacc_ccsd_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -133,10 +136,14 @@ int exacc_ccsd_residual(exacc_ccsd_t h, double* s1, double* s2, int ptr_on_devic
  * <ab||ie>, <am||ij> (the complex conjugates of the printed ones) and the
  * singles-triples term of E((T)) has the standard CCSD(T) sign.
  * FP64; needs the FP64 phase (INVALID_ARG while a mixed-precision handle is
- * still in its low-precision phase).  Temporary device memory: nocc * nvir^3
- * complex values for the <ab||ie> tiles plus nvir^3 for W, allocated and
- * freed inside the call (NOMEM if they do not fit).  Zero for nocc < 3 or
- * nvir < 3.  The amplitudes and the iteration state are not changed. */
+ * still in its low-precision phase).  The occupied space is split into blocks
+ * of n_red = opts.triples_occ_block spinors (section "Coupled cluster
+ * implementation": three nested loops over occupied subspaces, unique block
+ * triples only); the <ab||ie> tiles of the three current blocks (3 n_red nvir^3
+ * complex values, nocc nvir^3 when one block holds all) and at least one W row
+ * (nvir^3) are allocated and freed inside the call (NOMEM if that does not
+ * fit).  Zero for nocc < 3 or nvir < 3.  The amplitudes and the iteration
+ * state are not changed. */
 int exacc_ccsd_triples(exacc_ccsd_t h, double* e_plus_t, double* e_paren_t, double* e_minus_t);
 
 /* Lambda (left-hand) equations of CCSD at the current amplitudes (App. D,

@@ -865,23 +865,38 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out, double* ey_o
   if (h.phase32)
     raise(EXACC_ERR_INVALID_ARG,
           "triples need FP64 integrals: the handle is still in its low-precision phase");
-  const int o = h.P.o, v = h.P.v;
+  const int o = h.P.o, v = h.P.v, X = h.P.X;
   *e4_out = 0.0;
   *e5_out = 0.0;
   *ey_out = 0.0;
   if (o < 3 || v < 3) return;
+  if (h.op.triples_occ_block < 0) raise(EXACC_ERR_INVALID_ARG, "triples_occ_block < 0");
   const hipStream_t s = h.s;
   const int64_t vv = (int64_t)v * v, v3 = vv * v, ooo = (int64_t)o * o * o;
   const int nblk = triples_blocks(v);
   size_t free_b = 0, total_b = 0;
   HIPCHECK(hipMemGetInfo(&free_b, &total_b));
-  const size_t fixed = (size_t)(o * v3 + 2 * ooo + 2 * (int64_t)(o - 2) * nblk + 4) * 16 + (256u << 20);
-  if (fixed + (size_t)v3 * 16 > free_b)
-    raise(EXACC_ERR_NOMEM, "triples: the <ab||ie> tiles (nocc * nvir^3 complex) do not fit in free device memory");
-  // W rows (one per triple of a batch): what fits beside the tiles, at most o - 2
-  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(o - 2, (int64_t)((free_b - fixed) / 2 / (v3 * 16))));
+  const size_t small = (size_t)(2 * ooo + 2 * (int64_t)(o - 2) * nblk + 4) * 16 + (256u << 20);
+  const size_t row = (size_t)v3 * 16;
+  // occupied block size n_red: all of nocc when its tiles fit beside one W row, else the
+  // largest with three blocks of tiles resident (or the requested size)
+  int red = o;
+  if (small + (size_t)o * row + row > free_b) {
+    if (small + 4 * row > free_b)
+      raise(EXACC_ERR_NOMEM, "triples: three <ab||ie> tile rows and one W row do not fit in free device memory");
+    red = (int)std::min<int64_t>(o, (int64_t)((free_b - small - row) / (3 * row)));
+  }
+  if (h.op.triples_occ_block > 0) red = std::min(red, h.op.triples_occ_block);
+  const int nb_occ = (o + red - 1) / red;
+  const int slots = nb_occ == 1 ? 1 : 3;
+  const size_t tiles = (size_t)slots * red * row;
+  if (small + tiles + row > free_b)
+    raise(EXACC_ERR_NOMEM, "triples: the <ab||ie> tiles of three occupied blocks do not fit; lower triples_occ_block");
+  // W rows (one per triple of a batch): what fits beside the tiles, at most n_red
+  const int64_t cap = std::max<int64_t>(
+      1, std::min<int64_t>(std::min(red, o - 2), (int64_t)((free_b - small - tiles) / 2 / row)));
   h.use();
-  double* Ve = h.dalloc(o * v3);
+  double* Ve = h.dalloc((int64_t)slots * red * v3);
   double* W = h.dalloc(cap * v3);
   double* part = h.dalloc(2 * cap * nblk);  // 4 doubles per block
   double* tri = h.dalloc(2 * ooo);           // (e4, e5, ey, -) at [i][j][k]
@@ -895,45 +910,88 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out, double* ey_o
   // full t2 [i][j][a][b] into H4 (an FP64 work array rebuilt every iteration)
   k_unpack_full(h.x, h.x + 2 * (int64_t)o * v, nullptr, h.H4, o, v, s);
   Views<double> b = bviews(h, h.Bt);
-  // [i][a][b][e]: e contiguous, so the W GETTs read both operands along K
-  auto VeV = view(Ve, {o, v, v, v});
-  contract(s, "aiP,beP->iabe", ONE, b.Bvo, b.Bvv, false, VeV);
-  contract(s, "aeP,biP->iabe", MONE, b.Bvv, b.Bvo, true, VeV);
+  const int64_t nX = (int64_t)h.P.n * X;
+  // tiles <ab||ie> = (ai|be) - (ae|bi) of occupied block q into slot sl, [i][a][b][e]:
+  // e contiguous, so the W GETTs read both operands along K
+  int held[3] = {-1, -1, -1};
+  auto build = [&](int q, int sl) {
+    if (held[sl] == q) return;
+    const int i0 = q * red, ni = std::min(red, o - i0);
+    auto VeV = view(Ve + 2 * (int64_t)sl * red * v3, {ni, v, v, v});
+    auto Bvo_q = sview(b.Bvo.p + 2 * (int64_t)i0 * X, {v, ni, X}, {nX, X, 1});
+    contract(s, "aiP,beP->iabe", ONE, Bvo_q, b.Bvv, false, VeV);
+    contract(s, "aeP,biP->iabe", MONE, b.Bvv, Bvo_q, true, VeV);
+    held[sl] = q;
+  };
+  int slot_of[3] = {0, 0, 0};  // slot holding the tiles of the current K, J, I blocks
+  auto tile = [&](int i, int which) {
+    return Ve + 2 * ((int64_t)slot_of[which] * red + (i - (i / red) * red)) * v3;
+  };
   double* T2 = h.H4;
   const int64_t ovv = (int64_t)o * vv, oov = (int64_t)o * o * v, ov = (int64_t)o * v;
-  auto Vsl = [&](int i) { return sview(Ve + 2 * (int64_t)i * v3, {v, v, v}, {vv, (int64_t)v, 1}); };
+  auto Vsl = [&](double* p) { return sview(p, {v, v, v}, {vv, (int64_t)v, 1}); };
   // t_jk^{ce} as [c][e] (e contiguous); t_jk^{ec} = -t_jk^{ce}
   auto Tpair = [&](int j, int k) { return sview(T2 + 2 * ((int64_t)j * o + k) * vv, {v, v}, {(int64_t)v, 1}); };
   auto Tone = [&](int k) { return sview(T2 + 2 * (int64_t)k * ovv, {o, v, v}, {vv, (int64_t)v, 1}); };
   auto Vm = [&](int i, int j) {  // <ij||ma> as [m][a]; the terms use -conj of it
     return conj(sview(h.Vooov + 2 * ((int64_t)i * o + j) * ov, {o, v}, {(int64_t)v, 1}));
   };
-  for (int k = 2; k < o; ++k)
-    for (int j = 1; j < k; ++j)
-      for (int i0 = 0; i0 < j; i0 += (int)cap) {
-        const int ni = (int)std::min<int64_t>(cap, j - i0);
-        auto Wv = view(W, {ni, v, v, v});
-        // sum_e <ab||ie> t_jk^ec = -sum_e <ab||ie> t_jk^ce, i over the batch
-        contract(s, "iabe,ce->iabc", MONE, sview(Ve + 2 * (int64_t)i0 * v3, {ni, v, v, v}, {v3, vv, (int64_t)v, 1}),
-                 Tpair(j, k), false, Wv);
-        // sum_e <ab||je> t_ki^ec, t_ki^ce = T2[k][i][c][e]
-        contract(s, "abe,ice->iabc", MONE, Vsl(j),
-                 sview(T2 + 2 * ((int64_t)k * o + i0) * vv, {ni, v, v}, {vv, (int64_t)v, 1}), true, Wv);
-        // sum_e <ab||ke> t_ij^ec, t_ij^ce = T2[i][j][c][e]
-        contract(s, "abe,ice->iabc", MONE, Vsl(k),
-                 sview(T2 + 2 * ((int64_t)i0 * o + j) * vv, {ni, v, v}, {ovv, (int64_t)v, 1}), true, Wv);
-        // sum_m <am||ij> t_km^bc
-        contract(s, "ima,mbc->iabc", MONE,
-                 conj(sview(h.Vooov + 2 * ((int64_t)i0 * o + j) * ov, {ni, o, v}, {oov, (int64_t)v, 1})),
-                 Tone(k), true, Wv);
-        // sum_m <am||jk> t_im^bc
-        contract(s, "ma,imbc->iabc", MONE, Vm(j, k),
-                 sview(T2 + 2 * (int64_t)i0 * ovv, {ni, o, v, v}, {ovv, vv, (int64_t)v, 1}), true, Wv);
-        // sum_m <am||ki> t_jm^bc
-        contract(s, "ima,mbc->iabc", MONE,
-                 conj(sview(h.Vooov + 2 * ((int64_t)k * o + i0) * ov, {ni, o, v}, {ov, (int64_t)v, 1})),
-                 Tone(j), true, Wv);
-        k_triples_energy(W, h.Voovv, T2, h.x, h.eps, i0, ni, j, k, o, v, part, nblk, tri, s);
+  // three nested loops over occupied blocks, unique block triples bi <= bj <= bk
+  for (int bk = 0; bk < nb_occ; ++bk)
+    for (int bj = 0; bj <= bk; ++bj)
+      for (int bi = 0; bi <= bj; ++bi) {
+        if (slots == 1) {
+          build(0, 0);
+        } else {
+          build(bk, 0);
+          slot_of[0] = 0;
+          if (bj == bk) {
+            slot_of[1] = 0;
+          } else {
+            build(bj, 1);
+            slot_of[1] = 1;
+          }
+          if (bi == bk) {
+            slot_of[2] = 0;
+          } else if (bi == bj) {
+            slot_of[2] = slot_of[1];
+          } else {
+            build(bi, 2);
+            slot_of[2] = 2;
+          }
+        }
+        const int k_lo = std::max(bk * red, 2), k_hi = std::min(o, (bk + 1) * red);
+        for (int k = k_lo; k < k_hi; ++k) {
+          const int j_hi = std::min(k, std::min(o, (bj + 1) * red));
+          for (int j = std::max(bj * red, 1); j < j_hi; ++j) {
+            const int i_hi = std::min(j, std::min(o, (bi + 1) * red));
+            for (int i0 = bi * red; i0 < i_hi; i0 += (int)cap) {
+              const int ni = (int)std::min<int64_t>(cap, i_hi - i0);
+              auto Wv = view(W, {ni, v, v, v});
+              // sum_e <ab||ie> t_jk^ec = -sum_e <ab||ie> t_jk^ce, i over the batch
+              contract(s, "iabe,ce->iabc", MONE, sview(tile(i0, 2), {ni, v, v, v}, {v3, vv, (int64_t)v, 1}),
+                       Tpair(j, k), false, Wv);
+              // sum_e <ab||je> t_ki^ec, t_ki^ce = T2[k][i][c][e]
+              contract(s, "abe,ice->iabc", MONE, Vsl(tile(j, 1)),
+                       sview(T2 + 2 * ((int64_t)k * o + i0) * vv, {ni, v, v}, {vv, (int64_t)v, 1}), true, Wv);
+              // sum_e <ab||ke> t_ij^ec, t_ij^ce = T2[i][j][c][e]
+              contract(s, "abe,ice->iabc", MONE, Vsl(tile(k, 0)),
+                       sview(T2 + 2 * ((int64_t)i0 * o + j) * vv, {ni, v, v}, {ovv, (int64_t)v, 1}), true, Wv);
+              // sum_m <am||ij> t_km^bc
+              contract(s, "ima,mbc->iabc", MONE,
+                       conj(sview(h.Vooov + 2 * ((int64_t)i0 * o + j) * ov, {ni, o, v}, {oov, (int64_t)v, 1})),
+                       Tone(k), true, Wv);
+              // sum_m <am||jk> t_im^bc
+              contract(s, "ma,imbc->iabc", MONE, Vm(j, k),
+                       sview(T2 + 2 * (int64_t)i0 * ovv, {ni, o, v, v}, {ovv, vv, (int64_t)v, 1}), true, Wv);
+              // sum_m <am||ki> t_jm^bc
+              contract(s, "ima,mbc->iabc", MONE,
+                       conj(sview(h.Vooov + 2 * ((int64_t)k * o + i0) * ov, {ni, o, v}, {ov, (int64_t)v, 1})),
+                       Tone(j), true, Wv);
+              k_triples_energy(W, h.Voovv, T2, h.x, h.eps, i0, ni, j, k, o, v, part, nblk, tri, s);
+            }
+          }
+        }
       }
   std::vector<double> host(4 * ooo);
   HIPCHECK(hipMemcpyAsync(host.data(), tri, host.size() * sizeof(double), hipMemcpyDeviceToHost, s));

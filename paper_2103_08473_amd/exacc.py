@@ -38,6 +38,7 @@ class Opts(ctypes.Structure):
         ("timing", ctypes.c_int),
         ("doubles_only", ctypes.c_int),
         ("cc2", ctypes.c_int),
+        ("triples_occ_block", ctypes.c_int),
     ]
 
 

@@ -168,6 +168,8 @@ def main():
     ap.add_argument("--ref", default=None, help="compare every mode with a solve kept by --save")
     ap.add_argument("--triples", action="store_true",
                     help="after each solve, E(+T), E((T)) and E(-T) (App. C) with their time")
+    ap.add_argument("--triples-block", type=int, default=0,
+                    help="occupied block size n_red of the triples loops (0: as large as fits)")
     ap.add_argument("--lambda", dest="lam", action="store_true",
                     help="after each solve, the Lambda equations (App. D) and the density (App. E)")
     ap.add_argument("--time-limit", type=float, default=None,
@@ -191,6 +193,8 @@ def main():
     for mode in args.modes.split(","):
         log("solve %s" % mode)
         extra = {} if args.switch_tol is None else {"mixed_switch_tol": args.switch_tol}
+        if args.triples_block:
+            extra["triples_occ_block"] = args.triples_block
         res, t1, t2 = solve(eps_d, B_d, o, mode, args.tol, args.diis, args.max_iter, log,
                             time_limit=args.time_limit, triples=args.triples, lam=args.lam, **extra)
         if args.ref:

@@ -165,6 +165,26 @@ def test_triples_match_oracle(lib, o, v, X):
     assert abs(gm - em) <= 1e-12 * abs(e4)
 
 
+@pytest.mark.parametrize("block", [1, 2, 3, 4])
+def test_triples_occupied_blocks_match_oracle(lib, block):
+    """Three nested loops over occupied blocks of n_red spinors (tiles of three blocks
+    resident): every block size gives the oracle's E(+T), E((T)), E(-T), 1e-12 relative."""
+    from oracle.integrals import antisym
+    from oracle.triples import triples_energies
+    from paper_2103_08473_amd.exacc import CCSD
+    o, v, X = 7, 13, 30
+    say("triples blocks", block)
+    eps, B = make_system(o, v, X, seed=77, sigma=0.2)
+    t1, t2 = make_amplitudes(o, v, seed=78, scale=0.1)
+    n = o + v
+    ref = triples_energies(eps, antisym(B, slice(0, n), slice(0, n), slice(0, n), slice(0, n)), o, t1, t2)
+    with CCSD(eps, B, o, triples_occ_block=block) as cc:
+        cc.set_amplitudes(t1, t2)
+        got = cc.triples()
+    for g, r in zip(got, ref):
+        assert abs(g - r) <= 1e-12 * abs(ref[0])
+
+
 def test_ccsd_t_after_converged_solve(lib):
     """CCSD(T): converged GPU CCSD plus GPU triples vs the oracle's solve plus triples."""
     from oracle.integrals import antisym
