@@ -62,6 +62,7 @@ template void launch_gett<float>(const Gett<float>&, int, hipStream_t);
 
 using namespace exacc;
 typedef std::complex<double> zc;
+typedef std::complex<double> cplx_t;
 
 struct Buf {
   std::vector<double> d;
@@ -291,6 +292,143 @@ int main() {
     run("klcd,ld->kc", ONE, Vperm, t1, false, Hkc);
     run("aild,klcd->aikc", ONE, mk({v, o, o, v}), Vperm, true, H4);
     run("klcd,ijcd->klij", HALF, Vperm, TAU, true, Af);
+  }
+  // Lambda equations: preparation and residual (views as the library issues them)
+  {
+    const int64_t ov = (int64_t)o * v, oov = (int64_t)o * o * v, vv = (int64_t)v * v, ovv = ov * v;
+    const cplx_t NHALF(-0.5, 0), NQ(-0.25, 0);
+    auto U = mk({o, o, X}), Vt = mk({v, o, X});
+    auto Tq = mk({v, o, o, v});
+    auto T2v = sview(Tq.p, {o, o, v, v}, {ov, v, 1, oov});
+    auto Wqb = mk({v, o, o, v});
+    auto WqH = sview(Wqb.p, {v, o, o, v}, {1, v, ov, oov});
+    run("acP,kiP->aikc", MONE, Bvv, Boo, false, WqH);
+    run("aiP,kcP->aikc", ONE, Bvo, Bov, true, WqH);
+    run("acP,kiP->aikc", MONE, Bvv, U, true, WqH);
+    run("aiP,kcP->aikc", ONE, Vt, Bov, true, WqH);
+    run("klic,la->aikc", ONE, Vooov, t1, true, WqH);
+    run("aild,klcd->aikc", MONE, mk({v, o, o, v}), Voovv, true, WqH);
+    run("aild,klcd->aikc", NHALF, Tq, Voovv, true, WqH);
+    auto Wooov = mk({o, o, o, v});
+    run("if,mnfe->mnie", ONE, t1, Voovv, true, Wooov);
+    auto Cfb = mk({o, o, v, o});
+    const int64_t vo = (int64_t)v * o;
+    auto Cfji = sview(Cfb.p, {o, o, v, o}, {vo, o * vo, o, 1});
+    auto Afb = mk({o, o, o, o});
+    run("me,ijbe->ijbm", MONE, Hkc, T2v, true, Cfb);
+    run("nb,mnij->ijbm", MONE, t1, Afb, true, Cfb);
+    run("mnie,jnbe->ijbm", ONE, Vooov, T2v, true, Cfb);
+    run("mnie,jnbe->ijbm", MONE, Vooov, T2v, true, Cfji);
+    run("miP,bjP->ijbm", ONE, U, Bvo, true, Cfb);
+    run("mjP,biP->ijbm", MONE, Boo, Vt, true, Cfji);
+    auto Wt = mk({o, o, o, v});
+    run("ie,mnef->mnif", ONE, t1, Voovv, false, Wt);
+    run("mnif,njbf->ijbm", MONE, Wt, T2v, true, Cfb);
+    auto Bd = mk({v, v, X});
+    run("amP,me->aeP", MONE, conj(Bvo), t1, true, Bd);
+    // residual
+    auto Lq = mk({v, o, o, v});
+    auto L2v = sview(Lq.p, {o, o, v, v}, {ov, v, 1, oov});
+    auto l1 = mk({o, v});
+    auto Gv = mk({v, v}), Go = mk({o, o});
+    run("mnef,mnaf->ae", NHALF, T2v, L2v, false, Gv);
+    run("mnef,inef->mi", HALF, T2v, L2v, false, Go);
+    auto Zf = mk({o, o, v, v});
+    auto Zji = sview(Zf.p, {o, o, v, v}, {vv, ovv, v, 1});
+    auto Zba = sview(Zf.p, {o, o, v, v}, {ovv, vv, 1, v});
+    run("ijae,eb->ijab", ONE, L2v, Gac, true, Zf);
+    run("ijae,eb->ijab", MONE, L2v, Gac, true, Zba);
+    run("imab,jm->ijab", MONE, L2v, Gki, true, Zji);
+    auto M1 = mk({o, o});
+    run("ie,ne->in", ONE, l1, t1, false, M1);
+    run("in,njab->ijab", ONE, M1, Voovv, true, Zji);
+    run("ma,ijmb->ijab", MONE, l1, Wooov, true, Zf);
+    run("ijae,be->ijab", MONE, Voovv, Gv, true, Zba);
+    run("imab,mj->ijab", MONE, Voovv, Go, true, Zf);
+    auto Rv = mk({o, o, v, v});
+    run("aime,bjme->ijab", MONE, Lq, Wqb, false, Rv);
+    auto Yv = mk({o, v, X});
+    run("ie,aeP->iaP", ONE, l1, conj(Bvv), false, Yv);
+    run("iaP,jbP->ijab", ONE, Yv, Bov, true, Rv);
+    run("iaz,jbz->ijab", ONE, sview(l1.p, {o, v, 1}, {v, 1, 1}), sview(Hkc.p, {o, v, 1}, {v, 1, 1}), true, Rv);
+    auto l2p = mk({Po, Pv}), t2p = mk({Po, Pv}), LT = mk({Po, Po}), Znp2 = mk({Po, Pv});
+    run("py,qy->pq", ONE, l2p, t2p, false, LT);
+    run("pq,qx->px", ONE, LT, mk({Po, Pv}), false, Znp2);
+    run("pq,qx->px", ONE, mk({Po, Po}), l2p, true, Znp2);
+    auto S1l = mk({o, v});
+    run("imag,mg->ia", ONE, mk({o, o, v, v}), t1, true, S1l);
+    run("me,aime->ia", ONE, l1, Wqb, true, S1l);
+    run("imef,fmP->ieP", ONE, L2v, Bvo, false, Yv);
+    run("ieP,aeP->ia", ONE, Yv, conj(Bvv), true, S1l);
+    run("ni,na->ia", MONE, Go, Hkc, true, S1l);
+    auto LTo = mk({o, o, o, o});
+    run("imef,noef->imno", ONE, L2v, TAU, false, LTo);
+    run("imno,noma->ia", NQ, LTo, Vooov, true, S1l);
+    auto Z1 = mk({o, o, v, v});
+    run("fime,gnme->infg", ONE, Lq, Tq, false, Z1);
+    auto Q1 = mk({o, o, X});
+    run("infg,fgP->inP", ONE, Z1, Bvv, false, Q1);
+    run("inP,naP->ia", MONE, Q1, Bov, true, S1l);
+    run("infg,ngP->ifP", ONE, Z1, Bov, false, Yv);
+    run("ifP,faP->ia", ONE, Yv, Bvv, true, S1l);
+    auto Lt = mk({o, o, o, v}), M2 = mk({o, o, o, v});
+    run("imef,ne->imnf", ONE, L2v, t1, false, Lt);
+    run("imnf,fmP->inP", ONE, Lt, Bvo, false, Q1);
+    run("imnf,nmP->ifP", ONE, Lt, Boo, false, Yv);
+    run("imnf,omfg->inog", ONE, Lt, T2v, false, M2);
+    run("inog,noag->ia", ONE, M2, Voovv, true, S1l);
+    run("mnae,mnei->ia", NHALF, L2v, Cfb, true, S1l);
+    auto gP = mk({X}), gt = mk({o, v});
+    run("efP,ef->P", ONE, Bvv, Gv, false, gP);
+    run("iaP,P->ia", MONE, Bov, gP, true, S1l);
+    run("ef,ifP->ieP", ONE, Gv, Bov, false, Yv);
+    run("ef,ne->nf", ONE, Gv, t1, false, gt);
+    run("nf,nifa->ia", ONE, gt, Voovv, true, S1l);
+    run("mn,mina->ia", MONE, Go, Wooov, true, S1l);
+    // density pieces
+    run("me,ie->im", ONE, l1, t1, false, M1);
+    run("me,imae->ia", ONE, l1, T2v, true, gt);
+    run("im,ma->ia", MONE, Go, t1, true, gt);
+    run("ma,mb->ab", ONE, t1, l1, false, Gv);
+    // ladder tile build on the dressed factor rows (row stride v X)
+    {
+      const int a = 1, nb = v - a - 1;
+      auto Ba = sview(Bd.p + 2 * (int64_t)a * v * X, {v, X}, {X, 1});
+      auto Bb = sview(Bd.p + 2 * (int64_t)(a + 1) * v * X, {nb, v, X}, {(int64_t)v * X, X, 1});
+      run("cP,bdP->cbd", ONE, Ba, Bb, false, mk({v, nb, v}));
+    }
+  }
+  // perturbative triples: tiles of an occupied block and the W contractions of a batch
+  {
+    const int64_t vv = (int64_t)v * v, v3 = vv * v, ovv = (int64_t)o * vv, ov = (int64_t)o * v,
+                  oov = (int64_t)o * o * v;
+    const int i0 = 1, ni = 2, j = 2, k = 2;
+    auto Ve = mk({3, v, v, v});
+    auto VeV = view(Ve.p, {ni, v, v, v});
+    auto Bvo_q = sview(Bvo.p + 2 * (int64_t)i0 * X, {v, ni, X}, {nX, X, 1});
+    run("aiP,beP->iabe", ONE, Bvo_q, Bvv, false, VeV);
+    run("aeP,biP->iabe", MONE, Bvv, Bvo_q, true, VeV);
+    auto T2f = mk({o, o, v, v});
+    auto W = mk({ni, v, v, v});
+    run("iabe,ce->iabc", MONE, sview(Ve.p, {ni, v, v, v}, {v3, vv, (int64_t)v, 1}),
+        sview(T2f.p + 2 * ((int64_t)1 * o + k) * vv, {v, v}, {(int64_t)v, 1}), false, W);
+    run("abe,ice->iabc", MONE, sview(Ve.p + 2 * v3, {v, v, v}, {vv, (int64_t)v, 1}),
+        sview(T2f.p + 2 * ((int64_t)k * o + 0) * vv, {ni, v, v}, {vv, (int64_t)v, 1}), true, W);
+    run("abe,ice->iabc", MONE, sview(Ve.p, {v, v, v}, {vv, (int64_t)v, 1}),
+        sview(T2f.p + 2 * ((int64_t)0 * o + j) * vv, {ni, v, v}, {ovv, (int64_t)v, 1}), true, W);
+    run("ima,mbc->iabc", MONE, conj(sview(Vooov.p + 2 * ((int64_t)0 * o + j) * ov, {ni, o, v}, {oov, (int64_t)v, 1})),
+        sview(T2f.p + 2 * (int64_t)k * ovv, {o, v, v}, {vv, (int64_t)v, 1}), true, W);
+    run("ma,imbc->iabc", MONE, conj(sview(Vooov.p + 2 * ((int64_t)1 * o + 2) * ov, {o, v}, {(int64_t)v, 1})),
+        sview(T2f.p, {ni, o, v, v}, {ovv, vv, (int64_t)v, 1}), true, W);
+  }
+  // DF factors: transform and metric GEMMs, the Newton-Schulz product
+  {
+    const int m = 6, ns = 4, Xq = 5;
+    auto C = mk({m, ns}), J = mk({Xq, m, m}), T1 = mk({Xq, ns, m}), M = mk({Xq, ns, ns});
+    run("mp,Qmn->Qpn", ONE, conj(C), J, false, T1);
+    run("Qpn,nq->Qpq", ONE, T1, C, false, M);
+    run("PQ,Qx->Px", CPX, mk({Xq, Xq}), view(M.p, {Xq, (int64_t)ns * ns}), false, mk({Xq, (int64_t)ns * ns}));
+    run("ab,bc->ac", ONE, mk({Xq, Xq}), mk({Xq, Xq}), false, mk({Xq, Xq}));
   }
   // generic: conjugation, complex alpha, batch labels, empty sum
   run("zmk,zkn->zmn", CPX, conj(mk({3, 4, 5})), mk({3, 5, 6}), false, mk({3, 4, 6}));
