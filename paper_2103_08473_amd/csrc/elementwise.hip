@@ -649,6 +649,9 @@ void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipS
 //        + t_ki^ab t_j^c
 //   e4 += -6 |W~|^2 / D,  e5 += -6 Re(conj(Z~) W~) / D,  ey += 6 Re(conj(Y~) W~),
 //   D = e_a + e_b + e_c - e_i - e_j - e_k.
+// One workgroup per triple of 8-wide virtual tiles (tA <= tB <= tC): the three cubes
+// W[A][B][C], W[B][C][A] and W[C][A][B] are staged in LDS with 128-byte rows (every
+// global read coalesced), then each thread evaluates its a < b < c points.
 // Block partial sums (e4, e5, ey) to part[4 * (y * gridDim.x + block)].
 __global__ void triples_energy_kernel(const double* __restrict__ Wb, const double* __restrict__ Voovv,
                                       const double* __restrict__ T2, const double* __restrict__ t1,
@@ -681,18 +684,49 @@ __global__ void triples_energy_kernel(const double* __restrict__ Wb, const doubl
     r = add(r, mul(Tt(j, k, a, b), T1(i, c)));
     return add(r, mul(Tt(k, i, a, b), T1(j, c)));
   };
+  // tile triple of this workgroup
+  const int nt = (v + 7) / 8;
+  int rem = (int)blockIdx.x, ta = 0;
+  while (rem >= (nt - ta) * (nt - ta + 1) / 2) {
+    rem -= (nt - ta) * (nt - ta + 1) / 2;
+    ++ta;
+  }
+  int tb = ta;
+  while (rem >= nt - tb) {
+    rem -= nt - tb;
+    ++tb;
+  }
+  const int tc = tb + rem;
+  const int a0 = 8 * ta, b0 = 8 * tb, c0 = 8 * tc;
+  __shared__ double q0r[512], q0i[512], q1r[512], q1i[512], q2r[512], q2i[512];
+  for (int e = threadIdx.x; e < 512; e += TB) {
+    const int x = e >> 6, y = (e >> 3) & 7, w = e & 7;
+    z g0{0, 0}, g1{0, 0}, g2{0, 0};
+    if (a0 + x < v && b0 + y < v && c0 + w < v) g0 = Wl(a0 + x, b0 + y, c0 + w);
+    if (b0 + x < v && c0 + y < v && a0 + w < v) g1 = Wl(b0 + x, c0 + y, a0 + w);
+    if (c0 + x < v && a0 + y < v && b0 + w < v) g2 = Wl(c0 + x, a0 + y, b0 + w);
+    q0r[e] = g0.x;
+    q0i[e] = g0.y;
+    q1r[e] = g1.x;
+    q1i[e] = g1.y;
+    q2r[e] = g2.x;
+    q2i[e] = g2.y;
+  }
+  __syncthreads();
   double e4 = 0, e5 = 0, ey = 0;
   const double eo = eps[i] + eps[j] + eps[k];
-  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < v3; t += (int64_t)gridDim.x * TB) {
-    const int a = (int)(t / vv), b = (int)((t / v) % v), c = (int)(t % v);
-    if (!(a < b && b < c)) continue;
-    const z w = add(Wl(a, b, c), add(Wl(b, c, a), Wl(c, a, b)));
+  for (int e = threadIdx.x; e < 512; e += TB) {
+    const int x = e >> 6, y = (e >> 3) & 7, w = e & 7;
+    const int a = a0 + x, b = b0 + y, c = c0 + w;
+    if (!(c < v && a < b && b < c)) continue;
+    const int e1 = (y * 8 + w) * 8 + x, e2 = (w * 8 + x) * 8 + y;
+    const z wt{q0r[e] + q1r[e1] + q2r[e2], q0i[e] + q1i[e1] + q2i[e2]};
     const z zz = add(Zf(a, b, c), add(Zf(c, a, b), Zf(b, c, a)));
     const z yy = add(Yf(a, b, c), add(Yf(c, a, b), Yf(b, c, a)));
     const double D = eps[o + a] + eps[o + b] + eps[o + c] - eo;
-    e4 -= 6.0 * (w.x * w.x + w.y * w.y) / D;
-    e5 -= 6.0 * (zz.x * w.x + zz.y * w.y) / D;
-    ey += 6.0 * (yy.x * w.x + yy.y * w.y);
+    e4 -= 6.0 * (wt.x * wt.x + wt.y * wt.y) / D;
+    e5 -= 6.0 * (zz.x * wt.x + zz.y * wt.y) / D;
+    ey += 6.0 * (yy.x * wt.x + yy.y * wt.y);
   }
   __shared__ double s4[TB], s5[TB], sy[TB];
   s4[threadIdx.x] = e4;
@@ -747,7 +781,10 @@ __global__ void triples_reduce_kernel(const double* __restrict__ part, int nblk,
   }
 }
 
-int triples_blocks(int v) { return nblocks((int64_t)v * v * v, 1024); }
+int triples_blocks(int v) {
+  const int64_t nt = (v + 7) / 8;
+  return (int)(nt * (nt + 1) * (nt + 2) / 6);
+}
 
 void k_triples_energy(const double* W, const double* Voovv, const double* T2, const double* t1,
                       const double* eps, int i0, int ni, int j, int k, int o, int v, double* partial,
