@@ -1036,8 +1036,8 @@ static void lambda_alloc(Handle& h) {
   size_t fr = 0, tot = 0;
   HIPCHECK(hipMemGetInfo(&fr, &tot));
   if ((size_t)need * 16 + (256u << 20) > fr) raise(EXACC_ERR_NOMEM, "Lambda buffers do not fit");
-  Handle::Lam& L = h.lam;
-  L.lam = h.dalloc(h.P.L);
+  // into a local set first: the handle records them only once every allocation succeeded
+  Handle::Lam L;
   L.l1w = h.dalloc(o * v);
   L.s1 = h.dalloc(o * v);
   L.gt = h.dalloc(o * v);
@@ -1051,7 +1051,9 @@ static void lambda_alloc(Handle& h) {
   L.Q1 = h.dalloc(o * o * X);
   L.gP = h.dalloc(X);
   L.gam = h.dalloc((o + v) * (o + v));
+  L.lam = h.dalloc(h.P.L);
   dzero(h, L.lam, h.P.L);
+  h.lam = L;
 }
 
 static void lambda_check(Handle& h) {
