@@ -37,3 +37,31 @@ def test_create_rejects_bad_sizes_before_touching_the_device():
     assert L.exacc_ccsd_create(ctypes.byref(h), 0, 10, 10, None, None, ctypes.byref(o)) == -1
     assert not h.value
     assert b"nocc" in L.exacc_last_error()
+
+
+def test_df_factors_rejects_bad_sizes_before_touching_the_device():
+    L = exacc.load()
+    it = ctypes.c_int(0)
+    buf = (ctypes.c_double * 64)()
+    # nspinor > nao, naux < 1, null pointers: refused by the host checks
+    assert L.exacc_df_factors(3, 5, 2, buf, buf, buf, buf, 0, None, ctypes.byref(it)) == -1
+    assert L.exacc_df_factors(3, 2, 0, buf, buf, buf, buf, 0, None, ctypes.byref(it)) == -1
+    assert L.exacc_df_factors(3, 2, 2, None, buf, buf, buf, 0, None, ctypes.byref(it)) == -1
+    assert b"DF factors" in L.exacc_last_error()
+
+
+def test_new_options_default_to_automatic():
+    o = exacc.default_opts()
+    assert o.triples_occ_block == 0 and o.doubles_only == 0 and o.cc2 == 0
+
+
+def test_bench_runs_on_one_gpu_only():
+    """bench.py --gpus N with N > 1 exits with a message (before any device work)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
