@@ -124,7 +124,8 @@ int exacc_ccsd_set_amplitudes(exacc_ccsd_t h, const double* t1, const double* t2
  * them: s1 [nocc][nvir], s2 [nocc][nocc][nvir][nvir] (full, antisymmetric),
  * both including the diagonal Fock part.  Either may be NULL.  Contractions
  * run in the precision of the current phase (see exacc_ccsd_phase); the sum
- * with the driver and the diagonal part is formed in FP64. */
+ * with the inhomogeneous term <ab||ij> and the diagonal part is formed in
+ * FP64. */
 int exacc_ccsd_residual(exacc_ccsd_t h, double* s1, double* s2, int ptr_on_device);
 
 /* Perturbative triples corrections at the current amplitudes (App. C, working
