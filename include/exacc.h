@@ -211,6 +211,30 @@ int exacc_df_factors(int nao, int nspinor, int naux, const double* C, const doub
                      const double* V, double* B, int ptrs_on_device, void* stream,
                      int* ns_iterations);
 
+/* Bytes of the static device array that holds the temporaries of
+ * exacc_df_factors_noalloc: one such array per GPU the library runs on, held
+ * from library load to process end. */
+#define EXACC_DF_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* exacc_df_factors without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, serving loops that must not call
+ * hipMalloc, harnesses that forbid it.  Same operation, result and errors as
+ * exacc_df_factors with ptrs_on_device = 1: C, J, V and B are device pointers
+ * on the calling thread's current device, owned by the caller.  stream:
+ * hipStream_t, or NULL for the null stream.  Every temporary lives in the
+ * library's static array of EXACC_DF_SCRATCH_BYTES on that device; the call
+ * makes no device allocation and frees nothing.  Limit: the six naux x naux
+ * Newton-Schulz matrices plus one spinor row of the transform intermediates,
+ * 16 (6 naux^2 + naux (nao + nspinor)) bytes plus about 64 KiB, must fit in
+ * the array (naux up to about 1670); larger sizes return EXACC_ERR_NOMEM
+ * before any device work.  The transform runs over slices of spinor rows as
+ * wide as the array allows.  Calls on one GPU share the array and it keeps the
+ * last call's contents (nothing in it needs to start at zero): calls that
+ * overlap in time on one GPU, from different threads or streams, race and
+ * must be serialised by the caller. */
+int exacc_df_factors_noalloc(int nao, int nspinor, int naux, const double* C, const double* J,
+                             const double* V, double* B, void* stream, int* ns_iterations);
+
 /* Accumulated device time in ms of each stage since create (or the last
  * reset), measured with HIP events on the handle's stream; requires
  * opts.timing = 1.  names[k] (static strings) and ms[k] for k < *count.

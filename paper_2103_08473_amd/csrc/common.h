@@ -115,6 +115,10 @@ void k_triples_energy(const double* W, const double* Voovv, const double* T2, co
 // (all device pointers when on_device, else host); returns the Newton-Schulz step count
 int df_factors_impl(int m, int n, int X, const double* C, const double* J, const double* V, double* B,
                     bool on_device, hipStream_t s);
+// The same from device pointers with every temporary in the library's static per-GPU
+// scratch array (no device allocation); raises NOMEM when the sizes need more than it holds
+int df_factors_noalloc_impl(int m, int n, int X, const double* C, const double* J, const double* V,
+                            double* B, hipStream_t s);
 // dst[r][k] = conj(src[r * src_stride + k]) (complex elements)
 void k_conj_rows(double* dst, const double* src, int64_t rows, int64_t src_stride, int64_t len,
                  hipStream_t s);

@@ -1822,6 +1822,22 @@ int exacc_df_factors(int nao, int nspinor, int naux, const double* C, const doub
   });
 }
 
+int exacc_df_factors_noalloc(int nao, int nspinor, int naux, const double* C, const double* J,
+                             const double* V, double* B, void* stream, int* ns_iterations) {
+  return guarded([&] {
+    if (nao < 1 || nspinor < 1 || naux < 1 || nspinor > nao)
+      raise(EXACC_ERR_INVALID_ARG, "DF factors: need 1 <= nspinor <= nao and naux >= 1");
+    if (!C || !J || !V || !B) raise(EXACC_ERR_INVALID_ARG, "DF factors: null pointer");
+    if ((int64_t)naux * nao * nao > 0x7fffffffLL || (int64_t)naux * nspinor * nspinor > 0x7fffffffLL ||
+        (int64_t)naux * naux > 0x7fffffffLL)
+      raise(EXACC_ERR_INVALID_ARG, "DF factors: extent beyond 2^31");
+    const int it = df_factors_noalloc_impl(nao, nspinor, naux, C, J, V, B,
+                                           reinterpret_cast<hipStream_t>(stream));
+    if (ns_iterations) *ns_iterations = it;
+    return (int)EXACC_OK;
+  });
+}
+
 int exacc_ccsd_stage_times(exacc_ccsd_t hh, const char** names, double* ms, int* count, int reset) {
   return guarded([&] {
     if (!hh || !count) raise(EXACC_ERR_INVALID_ARG, "null argument");

@@ -73,6 +73,7 @@ def load():
     L.exacc_ccsd_set_lambda.argtypes = [P, P, P, I]
     L.exacc_ccsd_density.argtypes = [P, P, I]
     L.exacc_df_factors.argtypes = [I, I, I, P, P, P, P, I, P, ip]
+    L.exacc_df_factors_noalloc.argtypes = [I, I, I, P, P, P, P, P, ip]
     L.exacc_ccsd_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p), dp, ip, I]
     L.exacc_ccsd_phase.argtypes = [P, ip, ip]
     L.exacc_ccsd_phase.restype = I
@@ -87,7 +88,7 @@ def load():
               "exacc_ccsd_get_amplitudes", "exacc_ccsd_set_amplitudes", "exacc_ccsd_residual",
               "exacc_ccsd_triples", "exacc_ccsd_lambda_iterate", "exacc_ccsd_lambda_residual",
               "exacc_ccsd_get_lambda", "exacc_ccsd_set_lambda", "exacc_ccsd_density",
-              "exacc_df_factors",
+              "exacc_df_factors", "exacc_df_factors_noalloc",
               "exacc_ccsd_stage_times", "exacc_ccsd_destroy"):
         getattr(L, f).restype = I
     _lib = L
@@ -154,6 +155,23 @@ def df_factors(C, J, V, stream=None):
     B = np.zeros((X, n, n), np.complex128)
     _check(L.exacc_df_factors(nao, n, X, pc, pj, v.ctypes.data, B.ctypes.data, 0, None, ctypes.byref(it)))
     return B, it.value
+
+
+def df_factors_noalloc(C, J, V, B, stream=None):
+    """exacc_df_factors_noalloc on torch CUDA tensors: C complex128 [nao][n], J complex128
+    [naux][nao][nao], V float64 [naux][naux] and the caller's output B complex128
+    [naux][n][n] (written in place).  No device memory is allocated by the call.
+    Returns the Newton-Schulz step count."""
+    L = load()
+    it = ctypes.c_int(0)
+    nao, n = C.shape
+    X = J.shape[0]
+    assert tuple(B.shape) == (X, n, n) and tuple(V.shape) == (X, X) and tuple(J.shape) == (X, nao, nao)
+    for t in (C, J, V, B):
+        assert t.is_cuda and t.is_contiguous()
+    _check(L.exacc_df_factors_noalloc(nao, n, X, C.data_ptr(), J.data_ptr(), V.data_ptr(),
+                                      B.data_ptr(), stream, ctypes.byref(it)))
+    return it.value
 
 
 def _is_torch(x):
