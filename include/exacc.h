@@ -75,6 +75,14 @@ typedef struct {
   int    triples_occ_block;  /* perturbative triples: occupied block size n_red of the three nested
                                 block loops (<ab||ie> tiles of three blocks resident); 0 = the
                                 largest that fits in free device memory (all of nocc if possible) */
+  int    ladder_defect_correction; /* mixed precision, default 1: after the switch to FP64, one
+                                FP64 iteration stores the particle-ladder product L(tau_ref) of its
+                                amplitudes; the iterations that follow form every term in FP64 except
+                                the ladder, taken as L(tau_ref) + L_low(tau - tau_ref) with L_low in
+                                the low precision of the mode (its error shrinks with tau - tau_ref),
+                                until ||Delta|| <= tol or 4 of them bring no new lowest ||Delta||;
+                                then at least fp64_final_iters full FP64 iterations.  0: full FP64
+                                iterations from the switch on */
 } exacc_ccsd_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -241,13 +249,18 @@ int exacc_df_factors_noalloc(int nao, int nspinor, int naux, const double* C, co
  * Pass reset = 1 to zero the counters after reading. */
 int exacc_ccsd_stage_times(exacc_ccsd_t h, const char** names, double* ms, int* count, int reset);
 
-/* Precision of the contractions the next iterate() step will use: 1 = FP32
- * (mixed-precision phase), 0 = FP64.  *fp64_iters (may be NULL) receives the
- * number of FP64 iterations since the switch. */
+/* Precision of the contractions the next iterate() step will use: 1 = low
+ * precision (the FP32 / BF16x3 phase of a mixed mode), 2 = FP64 with the
+ * defect-corrected low-precision particle ladder (see
+ * ladder_defect_correction), 0 = FP64.  *fp64_iters (may be NULL) receives the
+ * number of full FP64 iterations since the last phase change. */
 int exacc_ccsd_phase(exacc_ccsd_t h, int* fp32, int* fp64_iters);
 
 /* Algorithmic flop count (real flops, 8 per complex multiply-add) of one
- * iteration's particle-particle ladder: tile build 2*naux*P_v^2 plus
+ * iteration's particle-particle ladder: the tile build of the blocks of
+ * <ab||cd> on and above the diagonal of the Hermitian pair matrix (for each
+ * virtual a, (ac|bd) over c, d >= a and b > a: naux * sum_{m=1}^{nvir}
+ * m^2 (m - 1) complex multiply-adds, about naux nvir^4 / 4) plus the
  * contraction P_o*P_v^2 complex multiply-adds, P_o = nocc(nocc-1)/2,
  * P_v = nvir(nvir-1)/2. */
 double exacc_ladder_flops(int nocc, int nvir, int naux);

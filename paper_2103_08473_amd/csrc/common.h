@@ -71,8 +71,9 @@ void launch_gett(const Gett<R>& g, int kind, hipStream_t s);
 int bf16x3_split_k(int K);
 void split_rows_bf16x3(const float* src, int64_t rows, int64_t group, int64_t group_stride,
                        int64_t row_stride, int K, unsigned short* dst, hipStream_t s);
+// B row of column n: (n / b_in) * b_outer + n % b_in (b_in <= 0: row n)
 void gemm_bf16x3_split(const unsigned short* A, const unsigned short* B, int M, int N, int K, float* C,
-                       int64_t ldc, hipStream_t s);
+                       int64_t ldc, hipStream_t s, int b_in = 0, int64_t b_outer = 0);
 
 // ---------------------------------------------------------------------------
 // Bandwidth kernels (elementwise.hip).  Sizes in elements; complex arrays are
@@ -90,8 +91,13 @@ template <typename T>
 void k_ring_operands(const T* T2, const double* t1, T* Tq, T* Xp, int o, int v, hipStream_t s);
 template <typename T>
 void k_expand_c(const T* Vooov, const T* Cp, T* Cf, int o, int v, hipStream_t s);
+// W[b'][(c<d)] = Ta[c][b'][d] - Ta[d][b'][c] over c, d < v, rows of W ldw apart
 template <typename T>
-void k_ladder_antisym(const T* Ta, T* W, int nb, int v, hipStream_t s);
+void k_ladder_antisym(const T* Ta, T* W, int nb, int v, int64_t ldw, hipStream_t s);
+// Wt[y][x] = W[x][col0 + y], x < rows, y < ncols (row strides ldw, ldt)
+template <typename T>
+void k_transpose_tail(const T* W, int64_t rows, int64_t ldw, int64_t col0, int64_t ncols, T* Wt,
+                      int64_t ldt, hipStream_t s);
 // S2 pieces of type T are summed in FP64 with the FP64 driver <ab||ij> and the
 // diagonal Fock part; writes the Jacobi step (or the full residual into s2_full).
 template <typename T>
@@ -126,6 +132,9 @@ void k_conj_rows(double* dst, const double* src, int64_t rows, int64_t src_strid
 void k_lambda_density(const double* Go, const double* M, const double* l1, const double* Dvo,
                       const double* Gv, const double* N, int o, int v, double* gamma, hipStream_t s);
 void k_cast(const double* in, float* out, int64_t nreal, hipStream_t s);
+// out = FP32(a - b), y += a + FP64(c) (c may be null), nreal reals
+void k_diff_cast(const double* a, const double* b, float* out, int64_t nreal, hipStream_t s);
+void k_add2(double* y, const double* a, const float* c, int64_t nreal, hipStream_t s);
 int assemble_t2_blocks(int64_t npairs);
 void k_reduce_sum(const double* partial, int n, int width, double* out, hipStream_t s);
 void k_dot_many(const double* const* es, int m, const double* e, int64_t len, double* partial,

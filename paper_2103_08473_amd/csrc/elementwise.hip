@@ -220,11 +220,12 @@ __global__ void expand_c_kernel(const T* __restrict__ Vooov, const T* __restrict
   }
 }
 
-// W[b'][x=(c<d)] = Ta[c][b'][d] - Ta[d][b'][c].  One block per (b', c-tile, d-tile) with
-// c-tile <= d-tile: both Ta tiles are read along their contiguous last index and
-// the second is transposed through LDS, so every global access is coalesced.
+// W[b'][x=(c<d)] = Ta[c][b'][d] - Ta[d][b'][c] (row stride ldw).  One block per (b', c-tile,
+// d-tile) with c-tile <= d-tile: both Ta tiles are read along their contiguous last index
+// and the second is transposed through LDS, so every global access is coalesced.
 template <typename T>
-__global__ void ladder_antisym_kernel(const T* __restrict__ Ta, T* __restrict__ W, int nb, int v) {
+__global__ void ladder_antisym_kernel(const T* __restrict__ Ta, T* __restrict__ W, int nb, int v,
+                                      int64_t ldw) {
   __shared__ double tr[32][33], ti[32][33];
   const int ntile = (v + 31) / 32;
   // blockIdx.x enumerates tile pairs (tc <= td) row-major
@@ -235,7 +236,6 @@ __global__ void ladder_antisym_kernel(const T* __restrict__ Ta, T* __restrict__ 
   }
   const int td = tc + rem;
   const int64_t bp = blockIdx.y;
-  const int64_t Pv = (int64_t)v * (v - 1) / 2;
   const int c0 = 32 * tc, d0 = 32 * td;
   const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
   // stage Ta[d][b'][c] for d in d-tile, c in c-tile (contiguous in c) as [c - c0][d - d0]
@@ -253,8 +253,31 @@ __global__ void ladder_antisym_kernel(const T* __restrict__ Ta, T* __restrict__ 
     if (c < v && d < v && c < d) {
       const z p = ld(Ta, ((int64_t)c * nb + bp) * v + d);
       const z q{tr[r][tx], ti[r][tx]};
-      st(W, bp * Pv + pidx(c, d, v), sub(p, q));
+      st(W, bp * ldw + pidx(c, d, v), sub(p, q));
     }
+  }
+}
+
+// Wt[y][x] = W[x][col0 + y] for x < rows, y < ncols (32 x 32 tiles through LDS: reads along
+// W rows and writes along Wt rows are both coalesced).
+template <typename T>
+__global__ void transpose_tail_kernel(const T* __restrict__ W, int64_t rows, int64_t ldw, int64_t col0,
+                                      int64_t ncols, T* __restrict__ Wt, int64_t ldt) {
+  __shared__ double tr[32][33], ti[32][33];
+  const int64_t x0 = 32 * (int64_t)blockIdx.y, y0 = 32 * (int64_t)blockIdx.x;
+  const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t x = x0 + r, y = y0 + tx;
+    if (x < rows && y < ncols) {
+      const z q = ld(W, x * ldw + col0 + y);
+      tr[r][tx] = q.x;
+      ti[r][tx] = q.y;
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t y = y0 + r, x = x0 + tx;
+    if (x < rows && y < ncols) st(Wt, y * ldt + x, z{tr[tx][r], ti[tx][r]});
   }
 }
 
@@ -520,6 +543,20 @@ __global__ void cast_kernel(const double* __restrict__ in, float* __restrict__ o
     out[t] = (float)in[t];
 }
 
+// out = FP32(a - b), n reals (the difference is formed in FP64, then rounded)
+__global__ void diff_cast_kernel(const double* __restrict__ a, const double* __restrict__ b,
+                                 float* __restrict__ out, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB)
+    out[t] = (float)(a[t] - b[t]);
+}
+
+// y += a (+ c, promoted to FP64, when c is given), n reals
+__global__ void add2_kernel(double* __restrict__ y, const double* __restrict__ a, const float* __restrict__ c,
+                            int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB)
+    y[t] += c ? a[t] + (double)c[t] : a[t];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -540,6 +577,16 @@ void k_lambda_density(const double* Go, const double* M, const double* l1, const
 void k_cast(const double* in, float* out, int64_t nreal, hipStream_t s) {
   if (nreal <= 0) return;
   hipLaunchKernelGGL(cast_kernel, dim3(nblocks(nreal)), dim3(TB), 0, s, in, out, nreal);
+  HIPCHECK(hipGetLastError());
+}
+void k_diff_cast(const double* a, const double* b, float* out, int64_t nreal, hipStream_t s) {
+  if (nreal <= 0) return;
+  hipLaunchKernelGGL(diff_cast_kernel, dim3(nblocks(nreal)), dim3(TB), 0, s, a, b, out, nreal);
+  HIPCHECK(hipGetLastError());
+}
+void k_add2(double* y, const double* a, const float* c, int64_t nreal, hipStream_t s) {
+  if (nreal <= 0) return;
+  hipLaunchKernelGGL(add2_kernel, dim3(nblocks(nreal)), dim3(TB), 0, s, y, a, c, nreal);
   HIPCHECK(hipGetLastError());
 }
 void k_transpose_B(const double* B, double* Bt, int64_t X, int64_t nn, hipStream_t s) {
@@ -592,12 +639,23 @@ void k_expand_c(const T* Vooov, const T* Cp, T* Cf, int o, int v, hipStream_t s)
 }
 
 template <typename T>
-void k_ladder_antisym(const T* Ta, T* W, int nb, int v, hipStream_t s) {
+void k_ladder_antisym(const T* Ta, T* W, int nb, int v, int64_t ldw, hipStream_t s) {
   if (nb <= 0 || v < 2) return;
   const int nt = (v + 31) / 32;
   if (nb > 65535) raise(-5, "ladder row too long");
   dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)nb), block(32, 8);
-  hipLaunchKernelGGL(ladder_antisym_kernel<T>, grid, block, 0, s, Ta, W, nb, v);
+  hipLaunchKernelGGL(ladder_antisym_kernel<T>, grid, block, 0, s, Ta, W, nb, v, ldw);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename T>
+void k_transpose_tail(const T* W, int64_t rows, int64_t ldw, int64_t col0, int64_t ncols, T* Wt,
+                      int64_t ldt, hipStream_t s) {
+  if (rows <= 0 || ncols <= 0) return;
+  const int64_t gx = (ncols + 31) / 32, gy = (rows + 31) / 32;
+  if (gx > 0x7fffffffLL || gy > 65535) raise(-5, "ladder tail too large to transpose");
+  hipLaunchKernelGGL(transpose_tail_kernel<T>, dim3((unsigned)gx, (unsigned)gy), dim3(32, 8), 0, s, W,
+                     rows, ldw, col0, ncols, Wt, ldt);
   HIPCHECK(hipGetLastError());
 }
 
@@ -860,7 +918,9 @@ void k_pack_amplitudes(const double* t1, const double* t2, double* x, int o, int
   template void k_unpack_tau<T>(const double*, const double*, T*, T*, T*, int, int, hipStream_t); \
   template void k_ring_operands<T>(const T*, const double*, T*, T*, int, int, hipStream_t);      \
   template void k_expand_c<T>(const T*, const T*, T*, int, int, hipStream_t);                    \
-  template void k_ladder_antisym<T>(const T*, T*, int, int, hipStream_t);                        \
+  template void k_ladder_antisym<T>(const T*, T*, int, int, int64_t, hipStream_t);               \
+  template void k_transpose_tail<T>(const T*, int64_t, int64_t, int64_t, int64_t, T*, int64_t,       \
+                                    hipStream_t);                                                 \
   template void k_assemble_t2<T>(const T*, const T*, const T*, const double*, const double*,     \
                                  const double*, int, int, double, double*, double*, double*,     \
                                  double*, int, hipStream_t);                                      \

@@ -100,7 +100,13 @@ static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
                         B16(oo * o * v)) / 2 + bvs;               // FP32 copies
   const size_t vovv_tmp = B16(p.vovv_chunk * vovv_row) + B16(p.vovv_chunk * o * p.Pv);
   const size_t create_peak = B16(n * n * X) * 2 + B16(p.oovv) + big32 + vovv_tmp;  // staging
-  const size_t phase64 = common + big64 + vovv_tmp;
+  // defect-corrected ladder after the switch: tau_ref and Zref, and the low-precision
+  // ladder operand (the split B_vv rows, or the FP32 factors) kept until it ends
+  const size_t dc = (mixed && op.ladder_defect_correction)
+                        ? 2 * B16(p.Po * p.Pv) +
+                              (op.precision == EXACC_MIXED_BF16X3 ? bvs : B16(n * n * X) / 2)
+                        : 0;
+  const size_t phase64 = common + big64 + vovv_tmp + dc;
   const size_t phase32 = common + big32;
   p.bytes_persistent = mixed ? phase32 : common + big64;
   p.bytes_peak = std::max(create_peak, mixed ? std::max(phase32, phase64) : phase64);
@@ -158,6 +164,14 @@ struct Handle {
   int fp64_iters = 0;         // FP64 iterations since the last switch
   double best32 = -1.0;       // lowest ||Delta|| of the low-precision phase so far
   int since_best32 = 0;       // low-precision iterations since that lowest value
+  // defect-corrected particle ladder after the switch (opts.ladder_defect_correction):
+  // dc = 1: the next FP64 iteration stores tau_ref and Zref = L(tau_ref); dc = 2: the ladder
+  // is Zref + L_low(tau - tau_ref); 0: off
+  int dc = 0;
+  bool last_dc = false;       // the last completed iteration used the corrected ladder
+  double best_dc = -1.0;
+  int since_best_dc = 0;
+  double *tau_ref = nullptr, *Zref = nullptr;
   // Lambda equations (App. D): buffers allocated on first use.  prepared: the
   // similarity-transformed Hamiltonian pieces (H4 = W_ovvo as [b][j][m][e], Cf = W_ovoo,
   // Ap = W_oooo packed, Gac/Gki/Hkc = F_vv/-F_oo/F_ov, Wooov, the dressed factor Bd) were
@@ -366,11 +380,11 @@ static void build_vovv_packed(Handle& h, T* dst) {
 }
 
 // FP64 classes for FP64 contractions (mixed modes: at the switch; the FP32 copies go)
-static void ensure_fp64_classes(Handle& h) {
+static void ensure_fp64_classes(Handle& h, bool keep_low_ladder = false) {
   if (h.Voovv && h.Vvovv_p) return;
   Scope sc(h, "switch_to_fp64");
-  h.dfree(h.Bvs);
-  h.dfree(h.Bt32);
+  if (!keep_low_ladder || !h.Bvs) h.dfree(h.Bvs);
+  if (!keep_low_ladder || h.Bvs) h.dfree(h.Bt32);
   h.dfree(h.Voooo32);
   h.dfree(h.Vooov32);
   h.dfree(h.Voovv32);
@@ -392,9 +406,17 @@ static void ensure_fp64_classes(Handle& h) {
 // b > a, antisymmetrised into W[(a,b)][(c<d)], then one GEMM per chunk of W rows.
 // bf: BF16x3 products; the pre-split rows h.Bvs (when present) are the factor B_vv itself
 // and may stand in for F only when use_bvs is set.
+// herm: the factors are Hermitian (F_ac = conj F_ca, true of B_vv), so W as a matrix over
+// pairs is Hermitian, <ab||cd> = conj <cd||ab>, and only its blocks on and above the
+// diagonal are built (ladder_apply_herm); the Lambda equations' T1-dressed factors are not
+// Hermitian and take the full build.
+template <typename R>
+static void ladder_apply_herm(Handle& h, const Work<R>& w, const R* F, int64_t row_stride,
+                              const TV<R>& Lp, R* Znp, bool bf, bool use_bvs);
 template <typename R>
 static void ladder_apply(Handle& h, const Work<R>& w, const R* F, int64_t row_stride, const TV<R>& Lp,
-                         R* Znp, bool bf, bool use_bvs) {
+                         R* Znp, bool bf, bool use_bvs, bool herm) {
+  if (herm) return ladder_apply_herm<R>(h, w, F, row_stride, Lp, Znp, bf, use_bvs);
   const int v = h.P.v, X = h.P.X;
   const int64_t Po = h.P.Po, Pv = h.P.Pv;
   const hipStream_t s = h.s;
@@ -428,11 +450,144 @@ static void ladder_apply(Handle& h, const Work<R>& w, const R* F, int64_t row_st
     }
     {
       Scope sc(h, "ladder_antisym");
-      k_ladder_antisym<R>(w.Ta, w.W + 2 * rows * Pv, nb, v, s);
+      k_ladder_antisym<R>(w.Ta, w.W + 2 * rows * Pv, nb, v, Pv, s);
     }
     rows += nb;
   }
   flush();
+}
+
+// Chunks [a0, a1) of virtual rows for the Hermitian ladder: W holds rows x Pw (Pw =
+// pairs of the w = v - a0 virtuals c, d >= a0) and, with the transposed tail, (Pw - rows)
+// x rows more; a chunk takes rows while that fits in cap elements (at least one row; the
+// W buffer holds one row of the first chunk in either layout).
+struct LadderChunk {
+  int a0, a1;
+  int64_t rows;
+};
+static std::vector<LadderChunk> ladder_chunks(int v, int64_t cap, bool tail) {
+  std::vector<LadderChunk> out;
+  for (int a0 = 0; a0 + 1 < v;) {
+    const int64_t Pw = npair(v - a0);
+    int a1 = a0;
+    int64_t rows = 0;
+    while (a1 + 1 < v) {
+      const int64_t r2 = rows + (v - a1 - 1);
+      if (rows > 0 && r2 * Pw + (tail ? (Pw - r2) * r2 : 0) > cap) break;
+      rows = r2;
+      ++a1;
+    }
+    out.push_back({a0, a1, rows});
+    a0 = a1;
+  }
+  return out;
+}
+
+// Packed index of the first pair (a, a + 1) over v virtuals.
+static inline int64_t pair_offset(int a, int v) { return (int64_t)a * v - (int64_t)a * (a + 1) / 2; }
+
+// The pairs (c<d) with c >= a0 are the tail [pair_offset(a0), P_v) of the packed pair
+// range, and the rows (a, b > a), a in [a0, a1), of a chunk are its first `rows` pairs.
+// Per chunk: for each a, Ta[c][b][d] = sum_P F_ac F_bd over c, d >= a0 and b > a
+// (w^2 (v - a - 1) naux complex multiply-adds instead of v^2 (v - a - 1) naux),
+// antisymmetrised into W[(a,b)][(c<d), c >= a0]; then
+//   forward:  Znp[:, (ab) in chunk] += Lp[:, tail] W^T           (all c >= a0)
+//   backward: Znp[:, (cd), c >= a1] += Lp[:, chunk] conj(W[:, c >= a1])
+// The backward product gives each later row the part of its sum over (c<d) in this chunk,
+// W[(cd)][(ab)] = conj W[(ab)][(cd)]; so every Znp column receives the sum over all pairs.
+// The backward product reads W through its transpose (K contiguous) for the BF16x3 GEMM,
+// directly (K strided) otherwise.
+template <typename R>
+static void ladder_apply_herm(Handle& h, const Work<R>& w, const R* F, int64_t row_stride,
+                              const TV<R>& Lp, R* Znp, bool bf, bool use_bvs) {
+  const int v = h.P.v, X = h.P.X;
+  const int64_t Po = h.P.Po, Pv = h.P.Pv;
+  const hipStream_t s = h.s;
+  if (Po == 0 || Pv == 0) return;
+  const int lad_build = bf ? GETT_LADDER_BUILD_BF16X3 : GETT_LADDER_BUILD;
+  const int lad_contract = bf ? GETT_LADDER_CONTRACT_BF16X3 : GETT_LADDER_CONTRACT;
+  const bool tail_t = bf;
+  // W buffer capacity in complex elements of R (the FP32 types alias the FP64 buffer)
+  const int64_t cap = h.P.chunk_pairs * Pv * (int64_t)(sizeof(double) / sizeof(R));
+  const int64_t ldl = Lp.str[0];
+  for (const LadderChunk& ch : ladder_chunks(v, cap, tail_t)) {
+    const int a0 = ch.a0, wv = v - a0;
+    const int64_t Pw = npair(wv), rows = ch.rows, off = pair_offset(a0, v);
+    int64_t xoff = 0;
+    for (int a = a0; a < ch.a1; ++a) {
+      const int nb = v - a - 1;
+      {
+        Scope sc(h, "ladder_build");
+        if (bf && use_bvs && h.Bvs) {  // pre-split rows B[(a, c)] and B[(b, d)], c, d >= a0
+          const int64_t rs = 4 * (int64_t)bf16x3_split_k(X);
+          gemm_bf16x3_split(h.Bvs + ((int64_t)a * v + a0) * rs, h.Bvs + ((int64_t)(a + 1) * v + a0) * rs,
+                            wv, nb * wv, X, reinterpret_cast<float*>(w.Ta), (int64_t)nb * wv, s, wv, v);
+        } else {
+          auto Ba = sview(const_cast<R*>(F) + 2 * ((int64_t)a * row_stride + (int64_t)a0 * X), {wv, X}, {X, 1});
+          auto Bb = sview(const_cast<R*>(F) + 2 * ((int64_t)(a + 1) * row_stride + (int64_t)a0 * X),
+                          {nb, wv, X}, {row_stride, X, 1});
+          contract(s, "cP,bdP->cbd", ONE, Ba, Bb, false, view(w.Ta, {wv, nb, wv}), lad_build);
+        }
+      }
+      {
+        Scope sc(h, "ladder_antisym");
+        k_ladder_antisym<R>(w.Ta, w.W + 2 * xoff * Pw, nb, wv, Pw, s);
+      }
+      xoff += nb;
+    }
+    Scope sc(h, "ladder_contract");
+    auto Lt = sview(Lp.p + 2 * off, {Po, Pw}, {ldl, 1});
+    contract(s, "py,xy->px", ONE, Lt, view(w.W, {rows, Pw}), true,
+             sview(Znp + 2 * off, {Po, rows}, {Pv, 1}), lad_contract);
+    const int64_t nt = Pw - rows;
+    if (nt > 0) {
+      auto Lc = sview(Lp.p + 2 * off, {Po, rows}, {ldl, 1});
+      auto Zt = sview(Znp + 2 * (off + rows), {Po, nt}, {Pv, 1});
+      if (tail_t) {
+        R* Wt = w.W + 2 * rows * Pw;
+        k_transpose_tail<R>(w.W, rows, Pw, rows, nt, Wt, rows, s);
+        contract(s, "px,yx->py", ONE, Lc, conj(view(Wt, {nt, rows})), true, Zt, lad_contract);
+      } else {
+        contract(s, "px,xy->py", ONE, Lc, conj(sview(w.W + 2 * rows, {rows, nt}, {Pw, 1})), true, Zt,
+                 lad_contract);
+      }
+    }
+  }
+}
+
+// The particle ladder of the FP64 iterations after a mixed-precision switch.  dc = 1: the
+// full FP64 product at the current amplitudes, kept as Zref = L(tau_ref) with tau_ref.
+// dc = 2: L(tau) = L(tau_ref) + L(tau - tau_ref), the second product in the mode's low
+// precision (FP32, or BF16x3 on the kept split rows) on the FP32 rounding of the FP64
+// difference tau - tau_ref; its rounding error is relative to |tau - tau_ref|, which is
+// about the step norm at the switch and does not grow as the iteration converges.  The
+// FP32 difference and product live in the H4 work array, free once the ring is done.
+static void ladder_defect_corrected(Handle& h, const Work<double>& w, const TV<double>& taup) {
+  const int64_t np = h.P.Po * h.P.Pv, nX = (int64_t)h.P.n * h.P.X;
+  if (np == 0) return;
+  if (h.dc == 1) {
+    Views<double> b = bviews(h, h.Bt);
+    dzero(h, h.Zref, np);
+    ladder_apply<double>(h, w, b.Bvv.p, nX, taup, h.Zref, false, true, true);
+    Scope sc(h, "ladder_dc");
+    k_add2(w.Znp, h.Zref, nullptr, 2 * np, h.s);
+    dcopy(h, h.tau_ref, w.taup, np);
+    return;
+  }
+  Work<float> w32 = work<float>(h);
+  float* dtau = reinterpret_cast<float*>(h.H4);
+  float* Zd = dtau + 2 * np;
+  {
+    Scope sc(h, "ladder_dc");
+    k_diff_cast(w.taup, h.tau_ref, dtau, 2 * np, h.s);
+    dzero(h, Zd, np);
+  }
+  const bool bf = h.op.precision == EXACC_MIXED_BF16X3 && h.Bvs;
+  const float* F = h.Bt32 ? bviews(h, h.Bt32).Bvv.p : nullptr;
+  if (!bf && !F) raise(EXACC_ERR_DEVICE, "defect-corrected ladder without its low-precision factors");
+  ladder_apply<float>(h, w32, F, nX, view(dtau, {h.P.Po, h.P.Pv}), Zd, bf, true, true);
+  Scope sc(h, "ladder_dc");
+  k_add2(w.Znp, h.Zref, Zd, 2 * np, h.s);
 }
 
 template <typename R>
@@ -598,7 +753,14 @@ static void compute_residual(Handle& h) {
   }
   // particle ladder: Znp[ij][ab] += sum_{c<d} tau[ij][cd] <ab||cd>, <ab||cd> = (ac|bd) - (ad|bc)
   // (BF16x3 products in the low-precision phase of the BF16x3 mode)
-  ladder_apply<R>(h, w, b.Bvv.p, (int64_t)h.P.n * X, taup, w.Znp, bf, true);
+  bool ladder_done = false;
+  if constexpr (sizeof(R) == sizeof(double)) {
+    if (h.dc != 0) {
+      ladder_defect_corrected(h, w, taup);
+      ladder_done = true;
+    }
+  }
+  if (!ladder_done) ladder_apply<R>(h, w, b.Bvv.p, (int64_t)h.P.n * X, taup, w.Znp, bf, true, true);
   if (ccd)
     dzero(h, w.S1, (int64_t)o * v);
   else
@@ -802,8 +964,21 @@ static int diis_slot(Handle& h) {
   return slot;
 }
 
+// Leave the defect-corrected phase: full FP64 iterations from here on; the reference
+// product and the low-precision ladder operands are released.
+static void end_defect_correction(Handle& h) {
+  HIPCHECK(hipStreamSynchronize(h.s));
+  h.dc = 0;
+  h.fp64_iters = 0;
+  h.dfree(h.tau_ref);
+  h.dfree(h.Zref);
+  h.dfree(h.Bvs);
+  h.dfree(h.Bt32);
+}
+
 static double one_iteration(Handle& h) {
   const bool was32 = h.phase32;
+  const int dc_now = h.dc;
   compute_residual_phase(h);
   const int slot = diis_slot(h);
   double* xt = h.slot_x(slot);
@@ -822,9 +997,14 @@ static double one_iteration(Handle& h) {
   // below the switch threshold or stops improving (no new lowest value for
   // kStall iterations: the rounding floor of the low-precision residual), then
   // FP64 contractions with a fresh DIIS subspace
+  // (with the defect-corrected ladder: one FP64 iteration that stores the reference
+  // ladder product, corrected iterations until ||Delta|| <= tol or they stall, then full
+  // FP64 iterations; the DIIS subspace carries over, the residual being the same to the
+  // corrected product's rounding)
   constexpr int kStall = 4;
   h.last32 = was32;
-  if (!was32) h.fp64_iters++;
+  h.last_dc = dc_now == 2;
+  if (!was32 && dc_now != 2) h.fp64_iters++;
   if (was32) {
     if (h.best32 < 0.0 || rnorm < h.best32) {
       h.best32 = rnorm;
@@ -834,12 +1014,30 @@ static double one_iteration(Handle& h) {
     }
   }
   if (was32 && (rnorm < h.op.mixed_switch_tol || h.since_best32 >= kStall)) {
-    ensure_fp64_classes(h);
+    const bool dc = h.op.ladder_defect_correction != 0 && !h.op.cc2 && h.P.Po * h.P.Pv > 0;
+    ensure_fp64_classes(h, dc);
+    if (dc) {
+      h.tau_ref = h.dalloc(h.P.Po * h.P.Pv);
+      h.Zref = h.dalloc(h.P.Po * h.P.Pv);
+      h.dc = 1;
+    }
     HIPCHECK(hipStreamSynchronize(h.s));
     timer_collect(h);
     h.phase32 = false;
     h.fp64_iters = 0;
     h.order.clear();
+  } else if (dc_now == 1) {
+    h.dc = 2;
+    h.best_dc = -1.0;
+    h.since_best_dc = 0;
+  } else if (dc_now == 2) {
+    if (h.best_dc < 0.0 || rnorm < h.best_dc) {
+      h.best_dc = rnorm;
+      h.since_best_dc = 0;
+    } else {
+      h.since_best_dc++;
+    }
+    if (rnorm <= h.op.tol || h.since_best_dc >= kStall) end_defect_correction(h);
   }
   return rnorm;
 }
@@ -1213,7 +1411,7 @@ static void lambda_compute(Handle& h) {
     auto LT = view(L.LTp, {Po, Po});
     contract(s, "py,qy->pq", ONE, l2v, view(h.x + 2 * ov, {Po, Pv}), false, LT);
     contract(s, "pq,qx->px", ONE, LT, view(h.Voovv_p, {Po, Pv}), false, Znp);
-    ladder_apply<double>(h, w, L.Bd, (int64_t)v * X, l2v, w.Znp, false, false);
+    ladder_apply<double>(h, w, L.Bd, (int64_t)v * X, l2v, w.Znp, false, false, false);
   }
   // ---- R1
   auto S1 = view(w.S1, {o, v});
@@ -1548,6 +1746,7 @@ void exacc_ccsd_default_opts(exacc_ccsd_opts* o) {
   o->doubles_only = 0;
   o->cc2 = 0;
   o->mixed_switch_tol = 1e-5;
+  o->ladder_defect_correction = 1;
 }
 
 size_t exacc_ccsd_memory_estimate(int nocc, int nvir, int naux, const exacc_ccsd_opts* opts) {
@@ -1592,7 +1791,7 @@ int exacc_ccsd_iterate(exacc_ccsd_t hh, int max_steps, int* steps_done, double* 
           r > 1e6 * std::max(h.first_norm, 1e-300))
         return (int)EXACC_ERR_DIVERGED;
       const int need = h.op.precision == EXACC_FP64 ? 0 : h.op.fp64_final_iters;
-      if (r <= h.op.tol && !h.last32 && h.fp64_iters >= need) {
+      if (r <= h.op.tol && !h.last32 && !h.last_dc && h.fp64_iters >= need) {
         if (converged) *converged = 1;
         return (int)EXACC_OK;
       }
@@ -1652,6 +1851,7 @@ int exacc_ccsd_set_amplitudes(exacc_ccsd_t hh, const double* t1, const double* t
     }
     HIPCHECK(hipStreamSynchronize(h.s));
     reset_diis(h);
+    if (h.dc == 2) h.dc = 1;  // the corrected ladder takes a new reference point
     return (int)EXACC_OK;
   });
 }
@@ -1859,7 +2059,7 @@ int exacc_ccsd_phase(exacc_ccsd_t hh, int* fp32, int* fp64_iters) {
   return guarded([&] {
     if (!hh) raise(EXACC_ERR_INVALID_ARG, "null handle");
     Handle& h = *reinterpret_cast<Handle*>(hh);
-    if (fp32) *fp32 = h.phase32 ? 1 : 0;
+    if (fp32) *fp32 = h.phase32 ? 1 : (h.dc == 2 ? 2 : 0);
     if (fp64_iters) *fp64_iters = h.fp64_iters;
     return (int)EXACC_OK;
   });
@@ -1867,7 +2067,9 @@ int exacc_ccsd_phase(exacc_ccsd_t hh, int* fp32, int* fp64_iters) {
 
 double exacc_ladder_flops(int nocc, int nvir, int naux) {
   const double Po = 0.5 * nocc * (nocc - 1.0), Pv = 0.5 * nvir * (nvir - 1.0);
-  return 8.0 * (2.0 * naux * Pv * Pv + Po * Pv * Pv);
+  // sum_{m=1}^{nvir} m^2 (m - 1) = (nvir (nvir + 1) / 2)^2 - nvir (nvir + 1) (2 nvir + 1) / 6
+  const double v = nvir, s3 = 0.25 * v * v * (v + 1) * (v + 1), s2 = v * (v + 1) * (2 * v + 1) / 6.0;
+  return 8.0 * (naux * (s3 - s2) + Po * Pv * Pv);
 }
 
 int exacc_ccsd_destroy(exacc_ccsd_t hh) {

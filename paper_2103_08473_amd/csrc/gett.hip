@@ -475,8 +475,10 @@ __device__ __forceinline__ int xcd_tile(int id, int n) {
   return x < tall ? x * per + l : tall * per + (x - tall) * (per - 1) + l;
 }
 
-// BM x BN workgroup tile, (BM/32) x (BN/32) waves of 32 x 32 outputs each
-template <int KIND, int BM, int BN, bool XCD>
+// BM x BN workgroup tile, (BM/32) x (BN/32) waves of 32 x 32 outputs each.  A16: operand
+// rows and bases are 16-byte aligned (one 16-byte load per k pair); otherwise each k pair
+// is read as two 8-byte complex values.
+template <int KIND, int BM, int BN, bool XCD, bool A16>
 __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32), (BM * BN == 64 * 64) ? 2 : 1) void
 gett_bf16x3_kernel(Gett<float> g) {
   constexpr int BK = 32;
@@ -519,12 +521,21 @@ gett_bf16x3_kernel(Gett<float> g) {
   typedef float f4v __attribute__((ext_vector_type(4)));
   f4v ra[QA], rb[QB];
   const int klen = ke - kb;
+  auto ld2 = [](const float* p) -> f4v {  // complex values k, k + 1 at p
+    if constexpr (A16) {
+      return *reinterpret_cast<const f4v*>(p);
+    } else {
+      const f2v_t u = *reinterpret_cast<const f2v_t*>(p);
+      const f2v_t w = *reinterpret_cast<const f2v_t*>(p + 2);
+      return f4v{u.x, u.y, w.x, w.y};
+    }
+  };
   auto ld = [&](const float* p, int k0) {
     // two consecutive complex (k, k+1) from k0 + kp; past the slice reads as zero
     const int k = k0 + kp;
     f4v v = {0.f, 0.f, 0.f, 0.f};
     if (k + 1 < klen) {
-      v = *reinterpret_cast<const f4v*>(p + 2 * k0);
+      v = ld2(p + 2 * k0);
     } else if (k < klen) {
       v.x = p[2 * k0];
       v.y = p[2 * k0 + 1];
@@ -534,9 +545,9 @@ gett_bf16x3_kernel(Gett<float> g) {
   auto load = [&](int k0) {  // k0: offset of the tile from kb
     if (k0 + BK <= klen) {   // whole tile inside the slice
 #pragma unroll
-      for (int q = 0; q < QA; ++q) ra[q] = *reinterpret_cast<const f4v*>(pa[q] + 2 * k0);
+      for (int q = 0; q < QA; ++q) ra[q] = ld2(pa[q] + 2 * k0);
 #pragma unroll
-      for (int q = 0; q < QB; ++q) rb[q] = *reinterpret_cast<const f4v*>(pb[q] + 2 * k0);
+      for (int q = 0; q < QB; ++q) rb[q] = ld2(pb[q] + 2 * k0);
     } else {  // ragged last tile (K may be odd)
 #pragma unroll
       for (int q = 0; q < QA; ++q) ra[q] = ld(pa[q], k0);
@@ -708,13 +719,13 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const float* __restrict
   }
 }
 
-// C[m][n] = sum_k A[m][k] B[n][k] over pre-split rows (row strides 4*Kp bf16),
-// C complex FP32 row-major with leading dimension ldc (complex elements).
-// BM x BN workgroup tile, (BM/32) x (BN/32) waves of 32 x 32 outputs each.
+// C[m][n] = sum_k A[m][k] B[n][k] over pre-split rows (row strides 4*Kp bf16), B row of n at
+// (n / b_in) * b_outer + n % b_in, C complex FP32 row-major with leading dimension ldc
+// (complex elements).  BM x BN workgroup tile, (BM/32) x (BN/32) waves of 32 x 32 outputs each.
 template <int BM, int BN, bool XCD>
 __global__ __launch_bounds__(64 * (BM / 32) * (BN / 32), (BM * BN == 64 * 64) ? 2 : 1) void
 gett_bf16x3_split_kernel(const unsigned short* __restrict__ A, const unsigned short* __restrict__ B, int M,
-                         int N, int Kp, float* __restrict__ C, int64_t ldc) {
+                         int N, int Kp, float* __restrict__ C, int64_t ldc, int b_in, int64_t b_outer) {
   constexpr int BK = 32;
   constexpr int WM = BM / 32, T = 64 * (BM / 32) * (BN / 32);
   constexpr int QA = BM * 16 / T, QB = BN * 16 / T, RS = T / 16;
@@ -740,8 +751,11 @@ gett_bf16x3_split_kernel(const unsigned short* __restrict__ A, const unsigned sh
   for (int q = 0; q < QA; ++q)
     pa[q] = reinterpret_cast<const u4v*>(A + min(m0 + tid / 16 + RS * q, M - 1) * rs) + ch;
 #pragma unroll
-  for (int q = 0; q < QB; ++q)
-    pb[q] = reinterpret_cast<const u4v*>(B + min(n0 + tid / 16 + RS * q, N - 1) * rs) + ch;
+  for (int q = 0; q < QB; ++q) {
+    const int n = min(n0 + tid / 16 + RS * q, N - 1);
+    const int nq = n / b_in;
+    pb[q] = reinterpret_cast<const u4v*>(B + ((int64_t)nq * b_outer + (n - nq * b_in)) * rs) + ch;
+  }
   u4v ra[QA], rb[QB];
   auto load = [&](int kt) {  // 16 chunks (256 bytes) per row and k tile
 #pragma unroll
@@ -837,19 +851,24 @@ void split_rows_bf16x3(const float* src, int64_t rows, int64_t group, int64_t gr
 }
 
 void gemm_bf16x3_split(const unsigned short* A, const unsigned short* B, int M, int N, int K, float* C,
-                       int64_t ldc, hipStream_t s) {
+                       int64_t ldc, hipStream_t s, int b_in, int64_t b_outer) {
   if (M <= 0 || N <= 0) return;
+  if (b_in <= 0) {  // B rows contiguous
+    b_in = N;
+    b_outer = N;
+  }
   // 128 x 128 tiles (16 waves, one workgroup per CU) in XCD order: 1.22x the
   // 64 x 64 tiles in plain order on the ladder tile build, bitwise equal
   constexpr int BM = 128, BN = 128;
   const int64_t tiles = (int64_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   if (tiles > 0x7fffffffLL) raise(-1, "contraction too large for one launch");
   hipLaunchKernelGGL((gett_bf16x3_split_kernel<BM, BN, true>), dim3((unsigned)tiles),
-                     dim3(64 * (BM / 32) * (BN / 32)), 0, s, A, B, M, N, bf16x3_split_k(K), C, ldc);
+                     dim3(64 * (BM / 32) * (BN / 32)), 0, s, A, B, M, N, bf16x3_split_k(K), C, ldc,
+                     b_in, b_outer);
   HIPCHECK(hipGetLastError());
 }
 
-template <int KIND>
+template <int KIND, bool A16>
 static void launch_bf16x3(const Gett<float>& g, hipStream_t s) {
   // 128 x 128 tiles in XCD order: 1.37x (contraction) and 1.25x (ring) the
   // 64 x 64 tiles in plain order, bitwise equal
@@ -882,7 +901,7 @@ static void launch_bf16x3(const Gett<float>& g, hipStream_t s) {
         h.ws = (float*)g_ws;
       }
     }
-    hipLaunchKernelGGL((gett_bf16x3_kernel<KIND, BM, BN, true>), dim3(tiles, nb, nz),
+    hipLaunchKernelGGL((gett_bf16x3_kernel<KIND, BM, BN, true, A16>), dim3(tiles, nb, nz),
                        dim3(64 * (BM / 32) * (BN / 32)), 0, s, h);
     HIPCHECK(hipGetLastError());
     if (nz > 1) {
@@ -901,23 +920,24 @@ void launch_gett(const Gett<R>& g, int kind_in, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.nbatch <= 0) return;
   if ((int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) > 0x7fffffffLL)
     raise(-1, "contraction too large for one launch");
-  // BF16x3 kinds: only for FP32 operands that are K-contiguous in both A and B
-  // (16-byte loads of two complex values: even row strides and 16-byte aligned bases)
-  const bool kcontig = g.k_in == g.K && g.a_ki == 1 && g.b_ki == 1 && g.a_mo % 2 == 0 &&
-                       g.a_mi % 2 == 0 && g.b_no % 2 == 0 && g.b_ni % 2 == 0 &&
-                       g.a_b % 2 == 0 && g.b_b % 2 == 0 &&
-                       reinterpret_cast<uintptr_t>(g.A) % 16 == 0 &&
-                       reinterpret_cast<uintptr_t>(g.B) % 16 == 0;
+  // BF16x3 kinds: only for FP32 operands that are K-contiguous in both A and B; 16-byte
+  // loads of two complex values where row strides are even and bases 16-byte aligned
+  const bool kcontig = g.k_in == g.K && g.a_ki == 1 && g.b_ki == 1;
+  const bool a16 = g.a_mo % 2 == 0 && g.a_mi % 2 == 0 && g.b_no % 2 == 0 && g.b_ni % 2 == 0 &&
+                   g.a_b % 2 == 0 && g.b_b % 2 == 0 && reinterpret_cast<uintptr_t>(g.A) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(g.B) % 16 == 0;
   if (kind == GETT_LADDER_BUILD_BF16X3 || kind == GETT_LADDER_CONTRACT_BF16X3 ||
       kind == GETT_RING_BF16X3) {
     if constexpr (sizeof(R) == sizeof(float)) {
       if (kcontig) {
         if (kind == GETT_LADDER_BUILD_BF16X3)
-          launch_bf16x3<GETT_LADDER_BUILD_BF16X3>(g, s);
+          a16 ? launch_bf16x3<GETT_LADDER_BUILD_BF16X3, true>(g, s)
+              : launch_bf16x3<GETT_LADDER_BUILD_BF16X3, false>(g, s);
         else if (kind == GETT_LADDER_CONTRACT_BF16X3)
-          launch_bf16x3<GETT_LADDER_CONTRACT_BF16X3>(g, s);
+          a16 ? launch_bf16x3<GETT_LADDER_CONTRACT_BF16X3, true>(g, s)
+              : launch_bf16x3<GETT_LADDER_CONTRACT_BF16X3, false>(g, s);
         else
-          launch_bf16x3<GETT_RING_BF16X3>(g, s);
+          a16 ? launch_bf16x3<GETT_RING_BF16X3, true>(g, s) : launch_bf16x3<GETT_RING_BF16X3, false>(g, s);
         return;
       }
     }

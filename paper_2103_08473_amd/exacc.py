@@ -39,6 +39,7 @@ class Opts(ctypes.Structure):
         ("doubles_only", ctypes.c_int),
         ("cc2", ctypes.c_int),
         ("triples_occ_block", ctypes.c_int),
+        ("ladder_defect_correction", ctypes.c_int),
     ]
 
 
@@ -332,10 +333,11 @@ class CCSD:
         return g
 
     def phase(self):
-        """(next step runs FP32 contractions, FP64 iterations since the switch)."""
+        """(precision of the next step: 1 low precision, 2 FP64 with the defect-corrected
+        low-precision ladder, 0 FP64; full FP64 iterations since the last phase change)."""
         a, b = ctypes.c_int(), ctypes.c_int()
         _check(self.L.exacc_ccsd_phase(self.h, ctypes.byref(a), ctypes.byref(b)))
-        return bool(a.value), b.value
+        return a.value, b.value
 
     def stage_times(self, reset=False):
         n = ctypes.c_int(64)

@@ -56,13 +56,13 @@ def solve(eps_d, B_d, nocc, mode, tol, diis, max_iter, log, time_limit=None, tri
     conv = False
     t1 = time.perf_counter()
     for it in range(1, max_iter + 1):
-        low = cc.phase()[0]
+        ph = ("fp64", "low", "dc")[cc.phase()[0]]
         ti = time.perf_counter()
         st, _, r, conv = cc.iterate(1)
         E = cc.energy()
-        hist.append((it, "low" if low else "fp64", E.real, E.imag, r, time.perf_counter() - ti))
+        hist.append((it, ph, E.real, E.imag, r, time.perf_counter() - ti))
         log("  %-13s it %3d %-4s E %.12f %+.3e i  |D| %.3e  t %.1fs" % (
-            mode, it, "low" if low else "fp64", E.real, E.imag, r, time.perf_counter() - t1))
+            mode, it, ph, E.real, E.imag, r, time.perf_counter() - t1))
         if conv or st == exacc.ERR_DIVERGED:
             break
         if time_limit is not None and time.time() - START > time_limit:
@@ -108,8 +108,11 @@ def solve(eps_d, B_d, nocc, mode, tol, diis, max_iter, log, time_limit=None, tri
     cc.close()
     low_t = [h[5] for h in hist if h[1] == "low"]
     hi_t = [h[5] for h in hist if h[1] == "fp64"]
+    dc_t = [h[5] for h in hist if h[1] == "dc"]
     return {"energy": [E.real, E.imag], "converged": conv, "iterations": len(hist),
-            "low_precision_iterations": len(low_t), "create_s": round(t_create, 3),
+            "low_precision_iterations": len(low_t), "defect_corrected_iterations": len(dc_t),
+            "s_per_dc_iter": round(float(np.mean(dc_t)), 4) if dc_t else None,
+            "create_s": round(t_create, 3),
             "iterate_s": round(t_iter, 3), "s_per_iter": round(t_iter / max(1, len(hist)), 4),
             "s_per_low_iter": round(float(np.mean(low_t)), 4) if low_t else None,
             "s_per_fp64_iter": round(float(np.mean(hi_t)), 4) if hi_t else None,

@@ -258,6 +258,23 @@ int main() {
     auto Zc = sview(Znp.p + 2 * start, {Po, rows}, {Pv, 1});
     run("py,xy->px", ONE, taup, W, true, Zc);
   }
+  // Hermitian ladder: the chunk's tile build over c, d >= a0, the forward product over the
+  // pair tail and the backward product through conj(W) (K strided) or its transpose
+  {
+    const int a0 = 1, a = 2, nb = v - a - 1, wv = v - a0;
+    const int64_t Pw = (int64_t)wv * (wv - 1) / 2, off = (int64_t)a0 * v - (int64_t)a0 * (a0 + 1) / 2;
+    const int64_t rows = 5, nt = Pw - rows;
+    auto Ba = sview(Bvv.p + 2 * ((int64_t)a * nX + (int64_t)a0 * X), {wv, X}, {X, 1});
+    auto Bb = sview(Bvv.p + 2 * ((int64_t)(a + 1) * nX + (int64_t)a0 * X), {nb, wv, X}, {nX, X, 1});
+    run("cP,bdP->cbd", ONE, Ba, Bb, false, mk({wv, nb, wv}));
+    auto W = mk({rows, Pw});
+    run("py,xy->px", ONE, sview(taup.p + 2 * off, {Po, Pw}, {Pv, 1}), W, true,
+        sview(Znp.p + 2 * off, {Po, rows}, {Pv, 1}));
+    auto Lc = sview(taup.p + 2 * off, {Po, rows}, {Pv, 1});
+    auto Zt = sview(Znp.p + 2 * (off + rows), {Po, nt}, {Pv, 1});
+    run("px,xy->py", ONE, Lc, conj(sview(W.p + 2 * rows, {rows, nt}, {Pw, 1})), true, Zt);
+    run("px,yx->py", ONE, Lc, conj(mk({nt, rows})), true, Zt);
+  }
   auto S1 = mk({o, v}), M1 = mk({o, o}), Y = mk({o, v, X});
   run("ac,ic->ia", ONE, Hac, t1, false, S1);
   run("ki,ka->ia", ONE, Hki, t1, true, S1);

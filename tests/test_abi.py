@@ -21,9 +21,13 @@ def test_host_only_entry_points():
     m2 = exacc.memory_estimate(40, 360, 1200)
     assert 0 < m1 < m2
     assert exacc.memory_estimate(0, 40, 120) == 0
-    # ladder flops: 8 * (2 X Pv^2 + Po Pv^2)
+    # ladder flops: 8 * (X sum_{m<=v} m^2 (m-1) + Po Pv^2): the Hermitian build (blocks on and
+    # above the pair diagonal) by direct summation, plus the contraction
     Po, Pv = 40 * 39 / 2, 360 * 359 / 2
-    assert abs(exacc.ladder_flops(40, 360, 1200) - 8 * (2 * 1200 * Pv ** 2 + Po * Pv ** 2)) < 1e3
+    build = 1200 * sum(m * m * (m - 1) for m in range(1, 361))
+    assert abs(exacc.ladder_flops(40, 360, 1200) - 8 * (build + Po * Pv ** 2)) < 1e3
+    # about half of the full build 2 X Pv^2
+    assert abs(build / (2 * 1200 * Pv ** 2) - 0.5) < 0.01
     L = exacc.load()
     assert L.exacc_status_string(0) == b"ok"
     assert L.exacc_status_string(-2).startswith(b"out of device memory")
