@@ -42,6 +42,7 @@ class Request:
     finished: float = math.nan
     energy: complex = 0j
     iterations: int = 0
+    device_ms: float = 0.0
     converged: bool = False
     status: int = 0
     mem: int = 0
@@ -67,6 +68,8 @@ def solve_one(req: Request, opts: dict):
             if conv or st == exacc.ERR_DIVERGED:
                 break
         req.energy = cc.energy()
+        if opts.get("timing"):   # HIP-event time of the request's stages on its own stream
+            req.device_ms = float(sum(cc.stage_times().values()))
     req.iterations, req.converged, req.status = it, conv, st
     return req
 

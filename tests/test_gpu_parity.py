@@ -43,17 +43,23 @@ def test_residual_matches_oracle(lib, o, v, X):
     assert abs(ge - E) <= 1e-12 * max(1.0, abs(E))
 
 
-@pytest.mark.parametrize("o,v,X,seed,sigma,iters", [
-    (10, 40, 120, 0, 0.05, 30),     # the (10, 40, 120) configuration, literal generator
-    (6, 50, 150, 1, None, 25),      # ragged tiles, size-scaled generator
+@pytest.mark.parametrize("o,v,X,seed,sigma,iters,shift,ndiis", [
+    (10, 40, 120, 0, 0.05, 30, 0.0, 8),     # the (10, 40, 120) configuration, literal generator
+    (6, 50, 150, 1, None, 25, 0.0, 8),      # ragged tiles, size-scaled generator
+    (6, 50, 150, 1, None, 25, 0.3, 8),      # level shift 0.3 (LSHIFT) in every denominator
+    (6, 50, 150, 1, 0.02, 25, 0.0, 0),      # plain Jacobi steps (no DIIS; sigma_B 0.02, where
+                                            # they converge)
+    (6, 50, 150, 1, 0.02, 25, 0.3, 0),      # plain Jacobi with the level shift
+    (5, 33, 99, 4, None, 20, 0.3, 3),       # both, with a DIIS subspace that drops pairs
 ])
-def test_iterations_match_oracle(lib, o, v, X, seed, sigma, iters):
-    """Energy after every iteration (MP2 start, Jacobi step, DIIS(8)) within 1e-10 Eh."""
+def test_iterations_match_oracle(lib, o, v, X, seed, sigma, iters, shift, ndiis):
+    """Energy after every iteration (MP2 start, Jacobi step with level shift s, DIIS of the
+    given size or none) within 1e-10 Eh."""
     from paper_2103_08473_amd.exacc import CCSD
-    say("iteration case", o, v, X, seed, sigma)
+    say("iteration case", o, v, X, seed, sigma, "shift", shift, "diis", ndiis)
     eps, B = make_system(o, v, X, seed=seed, sigma=sigma)
-    ref = oracle.solve(eps, B, o, max_iter=iters, tol=1e-10)
-    with CCSD(eps, B, o, tol=1e-10) as cc:
+    ref = oracle.solve(eps, B, o, max_iter=iters, tol=1e-10, diis_size=ndiis, level_shift=shift)
+    with CCSD(eps, B, o, tol=1e-10, level_shift=shift, diis_size=ndiis) as cc:
         _, conv, hist = cc.solve(max_iter=iters)
     assert len(hist) == len(ref.history)
     for (it, eg, rg), (_, eo, ro) in zip(hist, ref.history):
@@ -350,10 +356,11 @@ def test_mixed_precision_solve_matches_fp64_oracle(lib, o, v, X, seed):
         t1, t2 = cc.amplitudes()
         _, n64 = cc.phase()
     assert conv and n64 >= 3
-    assert phases[0] is True and phases[-1] is False
+    assert phases[0] == 1 and phases[-1] == 0
     dE = abs(e - ref.energy)
     dT = max(np.abs(t1 - ref.t1).max(), np.abs(t2 - ref.t2).max())
-    say("  iterations %d (fp32 %d), |dE| %.2e Eh, max|dT| %.2e" % (len(hist), sum(phases) + 1, dE, dT))
+    say("  iterations %d (fp32 %d, corrected ladder %d), |dE| %.2e Eh, max|dT| %.2e"
+        % (len(hist), phases.count(1) + 1, phases.count(2), dE, dT))
     assert dE <= 1e-7
     assert dT <= 1e-7
 
