@@ -1,23 +1,32 @@
-"""Benchmark: one CCSD amplitude iteration on one MI355X.
+"""Benchmark: the CCSD amplitude iteration on one MI355X, FP64 and mixed precision.
 
 A step is one pass of the whole iteration (eq. CC_general residual with the
 particle ladder built from density-fitting tiles, ring, intermediates,
 denominator step, DIIS, energy) for the nocc=40, nvir=360, naux=1200 system in
-complex FP64, with the inputs resident in HBM before the timed region.
+complex FP64, with the inputs resident in HBM before the timed region.  The
+timed steps are iterations of a solve that then runs on to convergence.
 
-Prints one JSON line.  value = ladder algorithmic TFLOP per iteration (tile
-build 2*naux*P_v^2 + contraction P_o*P_v^2 complex multiply-adds, 8 flops
-each) divided by the wall time of a whole iteration.  roofline = the ladder
-tile-build kernel (the dominant kernel), timed with HIP events on the
-library's stream during the timed region.  cpu_baseline = the CPU oracle's
-particle-ladder term on a bounded sample of rows of the same system.
+Prints one JSON line:
+  value         ladder algorithmic TFLOP per iteration (Hermitian tile build plus
+                contraction, exacc_ladder_flops) / wall time of a whole FP64 iteration;
+  roofline      the ladder tile-build kernel (the dominant kernel), timed with HIP
+                events on the library's stream during the timed steps;
+  solves        time to solution at ||Delta|| <= 1e-9 of the FP64, mixed FP32 and mixed
+                BF16x3 schedules, their iterations (low precision + FP64), |dE| and
+                max |dT| against the FP64 solve;
+  serving       a Poisson stream of requests of the serving configuration (continuous
+                batching, HBM admission), p50/p99 latency and solves/s;
+  clock         the GPU shader clock sampled during each leg;
+  cpu_baseline  the CPU oracle's particle-ladder term on a bounded sample of rows.
 """
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -29,65 +38,152 @@ PEAK_BF16_MFMA = 2516.6  # TFLOP/s, MI355X dense BF16 matrix
 WORKLOAD = dict(nocc=40, nvir=360, naux=1200, seed=0)
 
 
-# HBM bytes per ladder-build launch (mean over the 359 launches of one iteration),
-# from one rocprofv3 pass each of FETCH_SIZE and WRITE_SIZE, scaled by what the
-# counters read for a plain 1 GiB device copy (fetch x2.000, write x1.000), and
-# the kernel's MFMA-busy fraction and clock from a third pass.
-# They hold for the FP64 GETT source they were taken with: `gett_source_sha256`
-# hashes gett.hip up to the BF16x3 section, and the figure is reported as null
-# once that text differs.
-TRAFFIC = {"gett_source_sha256": "8bb8d67aeb59ee0bfa310edb2ecfd55e3877387fe5ad0c7983b8f0d45a1aa591",
-           "fetch_bytes": 8.1345e9, "write_bytes": 0.3770e9,
-           "mfma_busy": 0.716, "clock_ghz": 2.31}
+# HBM bytes per ladder-build launch (mean over the launches of one iteration), from one
+# rocprofv3 pass each of FETCH_SIZE and WRITE_SIZE, scaled by what the counters read for
+# a plain 1 GiB device copy (fetch x2.000, write x1.000), and the kernel's MFMA-busy
+# fraction and clock from a third pass.  They hold for the sources they were taken with:
+# `source_sha256` hashes the FP64 part of gett.hip (up to the BF16x3 section) and the
+# Hermitian ladder driver in exacc.cpp; the figures are reported as null once either
+# text differs.
+TRAFFIC = {"source_sha256": "8cbe9140a6e483dee6988f9f2a7dd5299329102f402cabd4bef76b3acf1ef2cf",
+           "fetch_bytes": 4.5737e9, "write_bytes": 0.2150e9,
+           "mfma_busy": 0.702, "clock_ghz": 2.33}
 GETT_SRC = os.path.join(ROOT, "paper_2103_08473_amd", "csrc", "gett.hip")
-BF16_MARK = "// BF16x3 complex GETT"
+EXACC_SRC = os.path.join(ROOT, "paper_2103_08473_amd", "csrc", "exacc.cpp")
+BF16_MARK = b"// BF16x3 complex GETT"
+LADDER_MARKS = (b"static void ladder_apply_herm(Handle& h, const Work<R>& w, const R* F, int64_t row_stride,\n"
+                b"                              const TV<R>& Lp, R* Znp, bool bf, bool use_bvs) {",
+                b"template <typename R>\nstatic void compute_residual(Handle& h) {")
 
 
-def gett_fp64_source_sha256():
+def kernel_source_sha256():
     import hashlib
     with open(GETT_SRC, "rb") as f:
-        text = f.read()
-    cut = text.find(BF16_MARK.encode())
-    return hashlib.sha256(text[:cut] if cut >= 0 else text).hexdigest()
+        g = f.read()
+    cut = g.find(BF16_MARK)
+    with open(EXACC_SRC, "rb") as f:
+        e = f.read()
+    i, j = e.find(LADDER_MARKS[0]), e.find(LADDER_MARKS[1])
+    return hashlib.sha256((g[:cut] if cut >= 0 else g) + (e[i:j] if 0 <= i < j else e)).hexdigest()
 
 
-def measured_traffic():
-    """Counter-derived HBM bytes per launch, or None if the kernel changed since."""
-    if gett_fp64_source_sha256() != TRAFFIC["gett_source_sha256"]:
+def measured_counters():
+    """Counter-derived HBM bytes per launch and MFMA-busy figures, or None if the kernel or
+    the ladder driver changed since they were taken."""
+    if TRAFFIC["source_sha256"] is None or kernel_source_sha256() != TRAFFIC["source_sha256"]:
         return None
-    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
-
-
-def measured_mfma_busy():
-    """MFMA-busy fraction of the tile-build kernel from SQ_VALU_MFMA_BUSY_CYCLES over
-    GRBM_GUI_ACTIVE x 1024 SIMDs (a separate rocprofv3 pass), and the clock that
-    GRBM_GUI_ACTIVE implies; None if the kernel changed since."""
-    if gett_fp64_source_sha256() != TRAFFIC["gett_source_sha256"]:
-        return None
-    return {"mfma_busy": TRAFFIC["mfma_busy"], "clock_ghz": TRAFFIC["clock_ghz"]}
+    return TRAFFIC
 
 
 def ladder_build_flops(o, v, X):
-    Pv = v * (v - 1) / 2
-    return 8.0 * 2.0 * X * Pv * Pv
+    """Algorithmic flops of the Hermitian tile build: for each virtual a, (ac|bd) over
+    c, d >= a, b > a (naux sum_m m^2 (m - 1), m = v - a), 8 per complex multiply-add."""
+    return 8.0 * X * sum(m * m * (m - 1) for m in range(1, v + 1))
 
 
 def ladder_build_bytes(o, v, X):
-    """Mean algorithmic HBM bytes of one tile-build launch (FP64 complex): read the
-    factor rows of a (v x X) and of all b > a ((v-a-1) v x X), write the v (v-a-1) v tile."""
-    rows_b = (v - 1) / 2.0  # mean of v-a-1 over a = 0..v-2
-    return 16.0 * (v * X + rows_b * v * X + v * rows_b * v)
+    """Mean algorithmic HBM bytes of one tile-build launch (FP64 complex) over the rows a:
+    read the factor rows (a, c >= a) and (b > a, d >= a), write the (v-a) (v-a-1) (v-a) tile."""
+    tot = 0.0
+    for a in range(v - 1):
+        m = v - a
+        tot += 16.0 * (m * X + (m - 1) * m * X + m * (m - 1) * m)
+    return tot / (v - 1)
 
 
-def cpu_baseline(eps, B, o, budget_s=20.0):
+class ClockSampler:
+    """Samples the GPU's current shader clock (the active level of pp_dpm_sclk in sysfs)
+    every 0.2 s on a host thread; legs are marked by name."""
+
+    def __init__(self):
+        self.path = None
+        try:
+            import torch
+            p = torch.cuda.get_device_properties(0)
+            bus = "%04x:%02x:%02x" % (getattr(p, "pci_domain_id", 0), p.pci_bus_id, p.pci_device_id)
+            for f in glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"):
+                if bus in os.path.realpath(os.path.dirname(f)):
+                    self.path = f
+                    break
+        except Exception:
+            self.path = None
+        self.samples, self.marks = [], []
+        self.stop = threading.Event()
+        self.t0 = time.perf_counter()
+        if self.path:
+            threading.Thread(target=self._run, daemon=True).start()
+
+    def _read(self):
+        with open(self.path) as f:
+            for line in f:
+                if line.rstrip().endswith("*"):
+                    return float(line.split(":")[1].strip().split("Mhz")[0].split("MHz")[0])
+        return None
+
+    def _run(self):
+        while not self.stop.is_set():
+            try:
+                mhz = self._read()
+                if mhz is not None:
+                    self.samples.append((time.perf_counter() - self.t0, mhz))
+            except Exception:
+                return
+            self.stop.wait(0.2)
+
+    def mark(self, name):
+        self.marks.append((name, time.perf_counter() - self.t0))
+
+    def report(self):
+        import numpy as np
+        self.stop.set()
+        if not self.path:
+            return {"source": None}
+        out = {"source": self.path, "unit": "MHz"}
+        ends = [t for _, t in self.marks[1:]] + [time.perf_counter() - self.t0]
+        for (name, t0), t1 in zip(self.marks, ends):
+            v = [m for t, m in self.samples if t0 <= t < t1]
+            if v:
+                out[name] = {"median": float(np.median(v)), "min": float(np.min(v)), "n": len(v)}
+        return out
+
+
+def host_info():
+    import platform
+    info = {"cpu_model": platform.processor() or "", "logical_cpus": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    try:
+        import psutil
+        info["physical_cores"] = psutil.cpu_count(logical=False)
+    except Exception:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if blas:
+            info["blas"] = "%s %s (%s), %d threads" % (blas[0].get("internal_api"), blas[0].get("version"),
+                                                      blas[0].get("architecture"), blas[0].get("num_threads"))
+            info["blas_threads"] = blas[0].get("num_threads")
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline(eps, B, o, budget_s=15.0):
     """Time the oracle's particle-ladder rows on the host, until ~budget_s of work."""
     import numpy as np
     from oracle.ccsd import ladder_rows
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    hi = host_info()
     n = eps.size
     v = n - o
     X = B.shape[0]
@@ -99,13 +195,75 @@ def cpu_baseline(eps, B, o, budget_s=20.0):
     flops = 0.0
     while time.perf_counter() - t0 < budget_s and rows < v - 1:
         ladder_rows(B, o, tau, rows, rows + 1)
-        flops += 8.0 * (v - rows - 1) * (2.0 * X * Pv + Po * Pv)
+        m = v - rows
+        # the same algorithmic work the GPU ladder counts for these rows: the Hermitian
+        # tile build of row a plus its share of the contraction
+        flops += 8.0 * (X * m * m * (m - 1) + Po * (m - 1) * Pv)
         rows += 1
     dt = time.perf_counter() - t0
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": "oracle particle ladder (1/2 sum <ab||cd> tau_ij^cd, <ab||cd> built from B) "
-                      "for virtual rows a=0..%d of the 40/360/1200 system, %.1f s; flops counted "
-                      "as the GPU ladder's algorithmic work for those rows" % (rows - 1, dt)}
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s",
+            "cores": int(hi.get("blas_threads") or hi.get("affinity_cpus") or 1), "kind": "oracle",
+            "host": hi,
+            "sample": "oracle particle ladder (1/2 sum <ab||cd> tau_ij^cd, <ab||cd> built from B, "
+                      "numpy complex128) for virtual rows a=0..%d of the 40/360/1200 system, %.1f s; "
+                      "flops counted as the GPU ladder's algorithmic work for those rows" % (rows - 1, dt)}
+
+
+def solve_leg(exacc, eps_d, B_d, o, stream, precision, tol, max_iter, progress, steps=0, warmup=0,
+              stop_after_timed=False):
+    """One solve to convergence from create; optionally the `steps` iterations after
+    `warmup` are the timed FP64 steps (stop_after_timed: end there, for profiler runs).
+    Returns a dict and the handle (open)."""
+    import torch
+    t_start = time.perf_counter()
+    cc = exacc.CCSD(eps_d, B_d, o, stream=stream.cuda_stream, timing=1, tol=tol, max_iter=max_iter,
+                    precision=precision)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t_start
+    hist, phases = [], []
+    timed = None
+    low_stages = None  # stage times of the low-precision phase (mixed schedules)
+    conv = False
+    cc.stage_times(reset=True)
+    while len(hist) < max_iter and not conv:
+        k = len(hist)
+        if steps and k == warmup:  # the timed steps: bracketed by device synchronisation
+            cc.stage_times(reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                st, n, r, conv = cc.iterate(1)
+                hist.append((len(hist) + 1, cc.energy(), r))
+            torch.cuda.synchronize()
+            timed = (time.perf_counter() - t0, cc.stage_times(reset=True), r)
+            if stop_after_timed:
+                break
+            continue
+        state = cc.phase()[0]  # 1 low precision, 2 corrected ladder, 0 FP64
+        ti = time.perf_counter()
+        st, n, r, conv = cc.iterate(1)
+        phases.append((state, time.perf_counter() - ti))
+        hist.append((len(hist) + 1, cc.energy(), r))
+        if state == 1 and cc.phase()[0] != 1:
+            low_stages = cc.stage_times(reset=True)
+        if st == exacc.ERR_DIVERGED:
+            break
+    torch.cuda.synchronize()
+    tts = time.perf_counter() - t_start
+    e = cc.energy()
+    _, n64 = cc.phase()
+    progress("  %d iterations, %.1f s, converged %s" % (len(hist), tts, conv))
+    def per(state):
+        t = [dt for st_, dt in phases if st_ == state]
+        return len(t), (round(sum(t) / len(t), 4) if t else None)
+    n_low, s_low = per(1)
+    n_dc, s_dc = per(2)
+    return {"converged": bool(conv), "iterations": len(hist), "low_precision_iterations": n_low,
+            "s_per_low_iter": s_low, "corrected_ladder_iterations": n_dc, "s_per_corrected_iter": s_dc,
+            "final_fp64_iterations": int(n64), "time_to_solution_s": round(tts, 3),
+            "create_s": round(t_create, 3), "energy": [e.real, e.imag],
+            "residual_last": hist[-1][2] if hist else None,
+            "low_stages": low_stages}, cc, timed
 
 
 def main():
@@ -114,7 +272,13 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="FP64 leg only")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="FP64 timed steps only (no solve to convergence, no other leg): for profiler runs")
+    ap.add_argument("--serving-requests", type=int, default=16)
+    ap.add_argument("--serving-rate", type=float, default=0.157,
+                    help="Poisson arrivals per second (0.8 x the 0.196 solves/s the serving stream "
+                         "sustained when saturated)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="first run one plain device-to-device copy of this many GiB (a known-size "
                          "kernel to scale hardware byte counters by)")
@@ -124,13 +288,19 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_2103_08473_amd import exacc
     from paper_2103_08473_amd.synth import make_system
 
+    def progress(msg):
+        print("bench: " + msg, file=sys.stderr, flush=True)
+
     o, v, X = WORKLOAD["nocc"], WORKLOAD["nvir"], WORKLOAD["naux"]
+    progress("inputs")
     eps, B = make_system(o, v, X, seed=WORKLOAD["seed"])
     torch.cuda.set_device(0)
+    clock = ClockSampler()
     if args.copy_calibration_gib > 0:
         nel = int(args.copy_calibration_gib * (1 << 30)) // 8
         src_t = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -141,67 +311,90 @@ def main():
     eps_d = torch.from_numpy(eps).cuda()
     B_d = torch.from_numpy(B).cuda()
     stream = torch.cuda.Stream()
-    def progress(msg):
-        print("bench: " + msg, file=sys.stderr, flush=True)
+    tol = 1e-9
 
-    progress("fp64 CCSD iterations")
-    cc = exacc.CCSD(eps_d, B_d, o, stream=stream.cuda_stream, timing=1, tol=1e-9)
-    for _ in range(args.warmup):
-        cc.iterate(1)
-    cc.stage_times(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = None
-    for _ in range(args.steps):
-        st, _, res, conv = cc.iterate(1)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    stages = cc.stage_times(reset=True)
+    # FP64 solve; its iterations warmup+1 .. warmup+steps are the timed steps
+    progress("fp64 solve (timed steps %d after %d warm-up iterations)" % (args.steps, args.warmup))
+    clock.mark("fp64")
+    max_iter = max(80, args.warmup + args.steps)
+    if args.no_solve:
+        args.no_mixed = True
+    s64, cc, timed = solve_leg(exacc, eps_d, B_d, o, stream, exacc.FP64, tol, max_iter, progress,
+                               steps=args.steps, warmup=args.warmup, stop_after_timed=args.no_solve)
+    dt, stages, res = timed
+    s64.pop("low_stages", None)
     E = cc.energy()
-    # Lambda equations (App. D) on the same handle, at these amplitudes: the first step
-    # also builds the transformed-Hamiltonian pieces, so it is the warm-up
-    lam = {}
+    t1_64, t2_64 = cc.amplitudes() if not args.no_mixed else (None, None)
+
+    extra = {}
     if not args.no_mixed:
+        # Lambda equations (App. D) at the converged amplitudes: the first step also builds
+        # the transformed-Hamiltonian pieces, so it is the warm-up
         progress("lambda iterations")
+        clock.mark("lambda")
         cc.lambda_iterate(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        nl = 3
+        for _ in range(nl):
             cc.lambda_iterate(1)
         torch.cuda.synchronize()
-        dtl = (time.perf_counter() - t0) / args.steps
-        sl = cc.stage_times(reset=True)
-        lam = {"lambda_fp64": {
-            "s_per_iter": round(dtl, 4),
-            "ccsd_iteration_time_ratio": round((dt / args.steps) / dtl, 3),
-            "stage_ms_per_iter": {k: round(t / (args.steps + 1), 2) for k, t in sl.items()}}}
+        dtl = (time.perf_counter() - t0) / nl
+        extra["lambda_fp64"] = {"s_per_iter": round(dtl, 4),
+                                "ccsd_iteration_time_ratio": round((dt / args.steps) / dtl, 3)}
     cc.close()
 
-    # CCD (the paper's CCDOUBLES) and CC2 variants: same system, FP64
-    ccd = {}
     if not args.no_mixed:
+        # CCD (the paper's CCDOUBLES) and CC2 variants: same system, FP64, 3 timed iterations
         for name, kw in (("ccd_fp64", {"doubles_only": 1}), ("cc2_fp64", {"cc2": 1})):
             progress(name)
-            cd = exacc.CCSD(eps_d, B_d, o, stream=stream.cuda_stream, timing=1, tol=1e-9, **kw)
-            for _ in range(args.warmup):
-                cd.iterate(1)
+            clock.mark(name)
+            cd = exacc.CCSD(eps_d, B_d, o, stream=stream.cuda_stream, tol=tol, **kw)
+            cd.iterate(1)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for _ in range(args.steps):
+            for _ in range(3):
                 cd.iterate(1)
             torch.cuda.synchronize()
-            dtc = (time.perf_counter() - t0) / args.steps
+            dtc = (time.perf_counter() - t0) / 3
             cd.close()
-            ccd[name] = {"s_per_iter": round(dtc, 4),
-                         "ccsd_iteration_time_ratio": round((dt / args.steps) / dtc, 3)}
+            extra[name] = {"s_per_iter": round(dtc, 4),
+                           "ccsd_iteration_time_ratio": round((dt / args.steps) / dtc, 3)}
 
-    # DF-factor generation (the step before the iteration) for the same spinor count:
-    # nao = 600 AO functions, nspinor = o + v = 400, naux = X.  Inputs made on the device
-    # with torch (J = L K, V = L L^T, orthonormal C); not part of the timed product.
-    dfleg = {}
+    solves = {"fp64": s64}
     if not args.no_mixed:
+        for name, prec in (("mixed_fp32", exacc.MIXED_FP32), ("mixed_bf16x3", exacc.MIXED_BF16X3)):
+            progress(name + " solve")
+            clock.mark(name)
+            sm, cm, _ = solve_leg(exacc, eps_d, B_d, o, stream, prec, tol, 80, progress)
+            st = sm.pop("low_stages") or {}
+            t1, t2 = cm.amplitudes()
+            cm.close()
+            e = complex(*sm["energy"])
+            sm["abs_dE_vs_fp64_Eh"] = abs(e - E)
+            sm["max_abs_dT1_vs_fp64"] = float(np.abs(t1 - t1_64).max())
+            sm["max_abs_dT2_vs_fp64"] = float(np.abs(t2 - t2_64).max())
+            sm["speedup_time_to_solution"] = round(s64["time_to_solution_s"] / sm["time_to_solution_s"], 3)
+            nlow = max(1, sm["low_precision_iterations"])
+            bms = st.get("ladder_build", float("nan"))
+            sm["low_phase_ms_per_iter"] = {k: round(t / nlow, 2) for k, t in st.items()}
+            if bms == bms:
+                btf = ladder_build_flops(o, v, X) / (bms / nlow * 1e-3) / 1e12
+                sm["low_phase_ladder_build_tflops"] = round(btf, 3)
+                if prec == exacc.MIXED_FP32:
+                    sm["low_phase_ladder_build_frac_fp32_peak"] = round(btf / PEAK_FP32_MFMA, 4)
+                else:  # 12 bf16 MFMA products (24 flops) per complex multiply-add
+                    sm["low_phase_ladder_build_hw_frac_bf16_peak"] = round(btf * 24 / 8 / PEAK_BF16_MFMA, 4)
+            solves[name] = sm
+            del t1, t2
+        del t1_64, t2_64
+
+        # DF-factor generation (the step before the iteration) for the same spinor count:
+        # nao = 600 AO functions, nspinor = o + v = 400, naux = X.  Inputs made on the device
+        # with torch (J = L K, V = L L^T, orthonormal C); not part of the timed product.
         try:
             progress("df factors")
+            clock.mark("df_factors")
             g = torch.Generator(device="cuda").manual_seed(5)
             nao, nsp = 600, o + v
             K = torch.randn((X, nao, nao), dtype=torch.complex128, device="cuda", generator=g) * 0.05
@@ -220,49 +413,35 @@ def main():
             torch.cuda.synchronize()
             dtd = time.perf_counter() - t0
             fl = 8.0 * (X * nsp * nao * nao + X * nsp * nsp * nao + X * X * nsp * nsp + nsit * 3.0 * X ** 3)
-            dfleg = {"df_factors": {"nao": nao, "nspinor": nsp, "naux": X, "seconds": round(dtd, 4),
-                                    "newton_schulz_steps": nsit, "tflops": round(fl / dtd / 1e12, 3),
-                                    "flops_counted": "complex GEMM work, 8 flops per multiply-add"}}
+            extra["df_factors"] = {"nao": nao, "nspinor": nsp, "naux": X, "seconds": round(dtd, 4),
+                                   "newton_schulz_steps": nsit, "tflops": round(fl / dtd / 1e12, 3),
+                                   "flops_counted": "complex GEMM work, 8 flops per multiply-add"}
             del J, Vm, Cq, Bdf, Lm
             torch.cuda.empty_cache()
         except Exception as ex:  # the headline line must still print
-            dfleg = {"df_factors": {"error": str(ex)[:200]}}
-
-    mixed = {}
-    if not args.no_mixed:
-        # same system, low-precision phases of the mixed schedules
-        for name, prec in (("mixed_fp32", exacc.MIXED_FP32), ("mixed_bf16x3", exacc.MIXED_BF16X3)):
-            progress(name)
-            cm = exacc.CCSD(eps_d, B_d, o, stream=stream.cuda_stream, timing=1, tol=1e-9,
-                            precision=prec)
-            for _ in range(args.warmup):
-                cm.iterate(1)
-            cm.stage_times(reset=True)
-            assert cm.phase()[0]
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                cm.iterate(1)
-            torch.cuda.synchronize()
-            dtm = (time.perf_counter() - t0) / args.steps
-            sm = cm.stage_times(reset=True)
-            cm.close()
-            bms = sm.get("ladder_build", float("nan")) / args.steps
-            btf = ladder_build_flops(o, v, X) / (bms * 1e-3) / 1e12
-            mixed[name] = {
-                "phase": ("fp32" if prec == exacc.MIXED_FP32 else "bf16x3 ladder, fp32 other")
-                         + " contractions, fp64 assembly/DIIS/energy",
-                "s_per_iter": round(dtm, 4),
-                "ladder_tflops_per_iter": round(exacc.ladder_flops(o, v, X) / dtm / 1e12, 3),
-                "speedup_vs_fp64": round((dt / args.steps) / dtm, 3),
-                "ladder_build_tflops": round(btf, 3),
-                "stage_ms_per_iter": {k: round(t / args.steps, 2) for k, t in sm.items()}}
-            if prec == exacc.MIXED_FP32:
-                mixed[name]["ladder_build_frac_fp32_peak"] = round(btf / PEAK_FP32_MFMA, 4)
-            else:  # 4 real products x 3 split terms = 12 bf16 MFMA products (24 flops) per
-                # complex multiply-add, against 8 algorithmic flops
-                mixed[name]["ladder_build_hw_frac_bf16_peak"] = round(btf * 24 / 8 / PEAK_BF16_MFMA, 4)
+            extra["df_factors"] = {"error": str(ex)[:200]}
     del B_d
+
+    serving = None
+    if not args.no_mixed and args.serving_requests > 0:
+        from paper_2103_08473_amd.serve import Request, report, run_stream
+        from paper_2103_08473_amd.synth import serving_request
+        progress("serving stream of %d requests at %.3f/s" % (args.serving_requests, args.serving_rate))
+        clock.mark("serving")
+        reqs = [Request(k, *serving_request(k)) for k in range(args.serving_requests)]
+        opts = dict(precision=exacc.MIXED_BF16X3, tol=1e-8, max_iter=80, timing=1)
+        t0 = time.perf_counter()
+        srv = run_stream(reqs, args.serving_rate, 200 << 30, 8, opts, producers=4)
+        makespan = time.perf_counter() - t0
+        serving = report(srv.done, makespan)
+        busy = sum(r.device_ms for r in srv.done) * 1e-3
+        serving.update({
+            "config": "requests 0..%d of the serving stream: nocc ~ U{6..40}, nvir = round(r nocc), "
+                      "r ~ U[5, 9], naux = 3 nvir, seed 1000+k; Poisson arrivals" % (args.serving_requests - 1),
+            "rate_per_s": args.serving_rate, "precision": "mixed bf16x3, fp64 refinement to 1e-8",
+            "max_active": 8, "hbm_budget_gb": 200,
+            "stage_time_sum_over_makespan": round(busy / makespan, 3),
+            "shapes": [[r.nocc, r.nvir, r.naux] for r in sorted(srv.done, key=lambda r: r.k)]})
 
     s_per_iter = dt / args.steps
     lad = exacc.ladder_flops(o, v, X)
@@ -271,6 +450,7 @@ def main():
     contract_ms = stages.get("ladder_contract", float("nan")) / args.steps
     achieved = ladder_build_flops(o, v, X) / (build_ms * 1e-3) / 1e12
     ladder_ms = build_ms + contract_ms + stages.get("ladder_antisym", 0.0) / args.steps
+    ctr = measured_counters()
     out = {
         "metric": "ladder TFLOP/s + s/CCSD iter, FP64 vs mixed at |dE|<=1e-7 Eh; p99 solve latency",
         "value": round(value, 3),
@@ -290,23 +470,27 @@ def main():
         "s_per_iter": round(s_per_iter, 4),
         "ladder_tflops_kernels": round(lad / (ladder_ms * 1e-3) / 1e12, 3),
         "dense_equiv_tflops": round(8.0 * o * o * v ** 4 / s_per_iter / 1e12, 3),
-        "residual_last": res,
+        "residual_last_timed": res,
         "energy": [E.real, E.imag],
         "stage_ms_per_iter": {k: round(t / args.steps, 2) for k, t in stages.items()},
         "roofline": {"bound": "mfma", "kernel": "ladder tile build (GETT kind 1)",
                      "achieved": round(achieved, 3), "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_MFMA, 4), "traffic": measured_traffic(),
+                     "frac": round(achieved / PEAK_FP64_MFMA, 4),
+                     "traffic": (ctr["fetch_bytes"] + ctr["write_bytes"]) if ctr else None,
                      "traffic_unit": "bytes per launch (HBM, counter-derived)",
-                     "algorithmic_bytes_per_launch": ladder_build_bytes(o, v, X),
-                     "flops_counted": "8 real flops per complex multiply-add (algorithmic); the "
-                                      "kernel's 3-multiplication complex product issues 6",
+                     "algorithmic_bytes_per_launch": round(ladder_build_bytes(o, v, X)),
+                     "flops_counted": "8 real flops per complex multiply-add of the Hermitian build "
+                                      "(blocks on and above the pair diagonal); the kernel's "
+                                      "3-multiplication complex product issues 6",
                      "hw_frac": round(0.75 * achieved / PEAK_FP64_MFMA, 4),
-                     "counters": measured_mfma_busy()},
+                     "counters": ({"mfma_busy": ctr["mfma_busy"], "clock_ghz": ctr["clock_ghz"]}
+                                  if ctr else None)},
+        "solves": solves,
     }
-    out.update(lam)
-    out.update(dfleg)
-    out.update(ccd)
-    out.update(mixed)
+    out.update(extra)
+    if serving is not None:
+        out["serving"] = serving
+    out["clock"] = clock.report()
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(eps, B, o)
