@@ -51,8 +51,10 @@ enum { EXACC_FP64 = 0, EXACC_MIXED_FP32 = 1, EXACC_MIXED_BF16X3 = 2 };
 typedef struct {
   int    precision;          /* EXACC_FP64 (default); EXACC_MIXED_FP32: FP32 contractions, then FP64;
                                 EXACC_MIXED_BF16X3: as MIXED_FP32 but the particle ladder's tile
-                                build and contraction use split-BF16 (hi*hi + hi*lo + lo*hi)
-                                products with FP32 accumulation */
+                                build and contraction, the o^3 v^3 ring contractions, the
+                                density-fitted terms of the ring intermediate and the vovv.tau
+                                product use split-BF16 (hi*hi + hi*lo + lo*hi) products with FP32
+                                accumulation */
   int    diis_size;          /* Pulay subspace size, default 8; 0 = plain Jacobi steps */
   int    max_iter;           /* .NCYCLES, default 30 */
   double tol;                /* .TCONVERG, default 1e-9, on ||Delta||_2 over the unique amplitudes */

@@ -111,11 +111,12 @@ void k_assemble_t1(const T* S1, const double* t1, const double* eps, int o, int 
 template <typename T>
 void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipStream_t s);
 // perturbative triples: (e4, e5, ey) of the occupied triples (i0 + y, j, k), y < ni, from
-// W[y][a][b][c] and the full T2; written to out[4 * (((i0 + y) * o + j) * o + k)]
+// the packed parts We[y][(a<b)][c], Wm[y][a][(b<c)] of W and the full T2; written to
+// out[4 * (((i0 + y) * o + j) * o + k)]
 int triples_blocks(int v);
-void k_triples_energy(const double* W, const double* Voovv, const double* T2, const double* t1,
-                      const double* eps, int i0, int ni, int j, int k, int o, int v, double* partial,
-                      int nblk, double* out, hipStream_t s);
+void k_triples_energy(const double* We, const double* Wm, const double* Voovv, const double* T2,
+                      const double* t1, const double* eps, int i0, int ni, int j, int k, int o, int v,
+                      double* partial, int nblk, double* out, hipStream_t s);
 // FP64 -> FP32, round to nearest even, nreal reals
 // DF factors B[X][n][n] from C [m][n], J [X][m][m] (complex) and the real metric V [X][X]
 // (all device pointers when on_device, else host); returns the Newton-Schulz step count

@@ -696,10 +696,12 @@ void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipS
 }
 
 // Perturbative triples (App. C), a batch of occupied triples (i0 + y, j, k), y < ni,
-// i0 + ni <= j < k, with W[y][a][b][c] (v^3 each) and the full T2 [i][j][a][b].
-// W~, Z~ and Y~ are fully antisymmetric in (a, b, c), so only a < b < c is
-// evaluated, with weight 6:
+// i0 + ni <= j < k, with W = We + Wm held packed: We[y][(a<b)][c] (the sum over e,
+// antisymmetric in (a, b)) and Wm[y][a][(b<c)] (the sum over m, antisymmetric in (b, c)),
+// Pv v each, and the full T2 [i][j][a][b].  W~, Z~ and Y~ are fully antisymmetric in
+// (a, b, c), so only a < b < c is evaluated, with weight 6:
 //   W~ = W[a,b,c] + W[b,c,a] + W[c,a,b]
+//      = We(ab,c) + We(bc,a) - We(ac,b) + Wm(a,bc) - Wm(b,ac) + Wm(c,ab)
 //   Z~ = Z(a,b,c) + Z(c,a,b) + Z(b,c,a),  Z(a,b,c) = <ab||ij> t_k^c + <ab||jk> t_i^c
 //        + <ab||ki> t_j^c with <ab||xy> = conj(<xy||ab>) from Voovv [x][y][a][b]
 //   Y~ = Y(a,b,c) + Y(c,a,b) + Y(b,c,a),  Y(a,b,c) = (1/3) sum over the permutations p
@@ -707,18 +709,22 @@ void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipS
 //        + t_ki^ab t_j^c
 //   e4 += -6 |W~|^2 / D,  e5 += -6 Re(conj(Z~) W~) / D,  ey += 6 Re(conj(Y~) W~),
 //   D = e_a + e_b + e_c - e_i - e_j - e_k.
-// One workgroup per triple of 8-wide virtual tiles (tA <= tB <= tC): the three cubes
-// W[A][B][C], W[B][C][A] and W[C][A][B] are staged in LDS with 128-byte rows (every
-// global read coalesced), then each thread evaluates its a < b < c points.
-// Block partial sums (e4, e5, ey) to part[4 * (y * gridDim.x + block)].
-__global__ void triples_energy_kernel(const double* __restrict__ Wb, const double* __restrict__ Voovv,
+// One workgroup per triple of 8-wide virtual tiles (tA <= tB <= tC): the six 8x8x8 cubes of
+// packed values that W~ needs on (A, B, C) are staged in LDS, each read with its
+// contiguous index fastest (every global read coalesced), then each thread evaluates its
+// a < b < c points.  Block partial sums (e4, e5, ey) to part[4 * (y * gridDim.x + block)].
+__global__ void triples_energy_kernel(const double* __restrict__ Web, const double* __restrict__ Wmb,
+                                      const double* __restrict__ Voovv,
                                       const double* __restrict__ T2, const double* __restrict__ t1,
                                       const double* __restrict__ eps, int i0, int j, int k, int o, int v,
                                       double* __restrict__ part) {
-  const int64_t vv = (int64_t)v * v, v3 = vv * v;
+  const int64_t vv = (int64_t)v * v, Pv = (int64_t)v * (v - 1) / 2;
   const int i = i0 + (int)blockIdx.y;
-  const double* __restrict__ W = Wb + 2 * (int64_t)blockIdx.y * v3;
-  auto Wl = [&](int a, int b, int c) { return ld(W, (int64_t)a * vv + (int64_t)b * v + c); };
+  const double* __restrict__ We = Web + 2 * (int64_t)blockIdx.y * Pv * v;
+  const double* __restrict__ Wm = Wmb + 2 * (int64_t)blockIdx.y * Pv * v;
+  // packed parts at p < q (p, q, r < v)
+  auto Ep = [&](int p, int q, int r) { return ld(We, pidx(p, q, v) * v + r); };
+  auto Mp = [&](int r, int p, int q) { return ld(Wm, (int64_t)r * Pv + pidx(p, q, v)); };
   auto Vc = [&](int x, int y, int a, int b) {  // <ab||xy> = conj(<xy||ab>)
     const z g = ld(Voovv, ((int64_t)x * o + y) * vv + (int64_t)a * v + b);
     return z{g.x, -g.y};
@@ -756,19 +762,41 @@ __global__ void triples_energy_kernel(const double* __restrict__ Wb, const doubl
   }
   const int tc = tb + rem;
   const int a0 = 8 * ta, b0 = 8 * tb, c0 = 8 * tc;
-  __shared__ double q0r[512], q0i[512], q1r[512], q1i[512], q2r[512], q2i[512];
+  // cube q at LDS index (x * 8 + y) * 8 + w holds its value for (a, b, c) = (a0+x, b0+y, c0+w);
+  // entries whose pair is not p < q (unused by a < b < c) are zero
+  __shared__ double qr[6][512], qi[6][512];
   for (int e = threadIdx.x; e < 512; e += TB) {
-    const int x = e >> 6, y = (e >> 3) & 7, w = e & 7;
-    z g0{0, 0}, g1{0, 0}, g2{0, 0};
-    if (a0 + x < v && b0 + y < v && c0 + w < v) g0 = Wl(a0 + x, b0 + y, c0 + w);
-    if (b0 + x < v && c0 + y < v && a0 + w < v) g1 = Wl(b0 + x, c0 + y, a0 + w);
-    if (c0 + x < v && a0 + y < v && b0 + w < v) g2 = Wl(c0 + x, a0 + y, b0 + w);
-    q0r[e] = g0.x;
-    q0i[e] = g0.y;
-    q1r[e] = g1.x;
-    q1i[e] = g1.y;
-    q2r[e] = g2.x;
-    q2i[e] = g2.y;
+    const int u = e >> 6, m = (e >> 3) & 7, f = e & 7;  // f fastest
+    z g[6];
+    int at[6];
+    // 0: We(ab, c), c fastest;  3: Wm(a, bc), c fastest;  4: Wm(b, ac), c fastest
+    {
+      const int a = a0 + u, b = b0 + m, c = c0 + f;
+      const bool in = a < v && b < v && c < v;
+      g[0] = (in && a < b) ? Ep(a, b, c) : z{0, 0};
+      g[3] = (in && b < c) ? Mp(a, b, c) : z{0, 0};
+      g[4] = (in && a < c) ? Mp(b, a, c) : z{0, 0};
+      at[0] = at[3] = at[4] = (u * 8 + m) * 8 + f;
+    }
+    // 1: We(bc, a), a fastest
+    {
+      const int b = b0 + u, c = c0 + m, a = a0 + f;
+      g[1] = (a < v && b < v && c < v && b < c) ? Ep(b, c, a) : z{0, 0};
+      at[1] = (f * 8 + u) * 8 + m;
+    }
+    // 2: We(ac, b), b fastest;  5: Wm(c, ab), b fastest
+    {
+      const int a = a0 + u, c = c0 + m, b = b0 + f;
+      const bool in = a < v && b < v && c < v;
+      g[2] = (in && a < c) ? Ep(a, c, b) : z{0, 0};
+      g[5] = (in && a < b) ? Mp(c, a, b) : z{0, 0};
+      at[2] = at[5] = (u * 8 + f) * 8 + m;
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      qr[q][at[q]] = g[q].x;
+      qi[q][at[q]] = g[q].y;
+    }
   }
   __syncthreads();
   double e4 = 0, e5 = 0, ey = 0;
@@ -777,8 +805,8 @@ __global__ void triples_energy_kernel(const double* __restrict__ Wb, const doubl
     const int x = e >> 6, y = (e >> 3) & 7, w = e & 7;
     const int a = a0 + x, b = b0 + y, c = c0 + w;
     if (!(c < v && a < b && b < c)) continue;
-    const int e1 = (y * 8 + w) * 8 + x, e2 = (w * 8 + x) * 8 + y;
-    const z wt{q0r[e] + q1r[e1] + q2r[e2], q0i[e] + q1i[e1] + q2i[e2]};
+    const z wt{qr[0][e] + qr[1][e] - qr[2][e] + qr[3][e] - qr[4][e] + qr[5][e],
+               qi[0][e] + qi[1][e] - qi[2][e] + qi[3][e] - qi[4][e] + qi[5][e]};
     const z zz = add(Zf(a, b, c), add(Zf(c, a, b), Zf(b, c, a)));
     const z yy = add(Yf(a, b, c), add(Yf(c, a, b), Yf(b, c, a)));
     const double D = eps[o + a] + eps[o + b] + eps[o + c] - eo;
@@ -844,12 +872,12 @@ int triples_blocks(int v) {
   return (int)(nt * (nt + 1) * (nt + 2) / 6);
 }
 
-void k_triples_energy(const double* W, const double* Voovv, const double* T2, const double* t1,
-                      const double* eps, int i0, int ni, int j, int k, int o, int v, double* partial,
-                      int nblk, double* out, hipStream_t s) {
+void k_triples_energy(const double* We, const double* Wm, const double* Voovv, const double* T2,
+                      const double* t1, const double* eps, int i0, int ni, int j, int k, int o, int v,
+                      double* partial, int nblk, double* out, hipStream_t s) {
   if (ni <= 0) return;
-  hipLaunchKernelGGL(triples_energy_kernel, dim3(nblk, ni), dim3(TB), 0, s, W, Voovv, T2, t1, eps, i0, j,
-                     k, o, v, partial);
+  hipLaunchKernelGGL(triples_energy_kernel, dim3(nblk, ni), dim3(TB), 0, s, We, Wm, Voovv, T2, t1, eps, i0,
+                     j, k, o, v, partial);
   HIPCHECK(hipGetLastError());
   hipLaunchKernelGGL(triples_reduce_kernel, dim3(ni), dim3(TB), 0, s, partial, nblk, i0, j, k, o, out);
   HIPCHECK(hipGetLastError());

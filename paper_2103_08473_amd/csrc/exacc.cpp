@@ -599,6 +599,9 @@ static void compute_residual(Handle& h) {
   // BF16x3 products for the ladder and ring in the low-precision phase of the BF16x3 mode
   const bool bf = sizeof(R) == sizeof(float) && h.op.precision == EXACC_MIXED_BF16X3;
   const int ring_kind = bf ? GETT_RING_BF16X3 : GETT_RING;
+  // the density-fitted o^2 v^2 naux terms of the ring intermediate and the vovv . tau
+  // product of C^{kb}_{ij} (K contiguous in both operands) also take BF16x3 products there
+  const int df_kind = bf ? GETT_RING_BF16X3 : GETT_GENERIC;
   // CCD: t1 is zero, so every contraction with a t1 (or U, Vt, y) factor is skipped
   const bool ccd = h.op.doubles_only != 0;
   Views<R> b = bviews(h, w.Bt);
@@ -692,11 +695,11 @@ static void compute_residual(Handle& h) {
   {
     Scope sc(h, "ring_build");
     // <ak||ci> = (ac|ki) - (ai|kc), formed from the factors each iteration
-    contract(s, "acP,kiP->aikc", ONE, b.Bvv, b.Boo, false, H4);
-    contract(s, "aiP,kcP->aikc", MONE, b.Bvo, b.Bov, true, H4);
+    contract(s, "acP,kiP->aikc", ONE, b.Bvv, b.Boo, false, H4, df_kind);
+    contract(s, "aiP,kcP->aikc", MONE, b.Bvo, b.Bov, true, H4, df_kind);
     if (!ccd) {
-      contract(s, "acP,kiP->aikc", ONE, b.Bvv, U, true, H4);
-      contract(s, "aiP,kcP->aikc", MONE, Vt, b.Bov, true, H4);
+      contract(s, "acP,kiP->aikc", ONE, b.Bvv, U, true, H4, df_kind);
+      contract(s, "aiP,kcP->aikc", MONE, Vt, b.Bov, true, H4, df_kind);
       contract(s, "klic,la->aikc", MONE, Vooov, t1, true, H4);
     }
     contract(s, "aild,klcd->aikc", ONE, view(w.Xp, {v, o, o, v}), Voovv, true, H4, ring_kind);
@@ -705,7 +708,7 @@ static void compute_residual(Handle& h) {
   {
     Scope sc(h, "ring");
     contract(s, "aikc,bjkc->ijab", ONE, H4, view(w.Tq, {v, o, o, v}), false, Rv, ring_kind);
-    if (!ccd) contract(s, "aiP,bjP->ijab", ONE, Vt, b.Bvo, true, Rv);
+    if (!ccd) contract(s, "aiP,bjP->ijab", ONE, Vt, b.Bvo, true, Rv, df_kind);
   }
   // Z and its views with i<->j or a<->b swapped: a term X launched into Z and,
   // negated, into a swapped view accumulates P^-_ij X (or P^-_ab X) directly
@@ -723,7 +726,7 @@ static void compute_residual(Handle& h) {
   if (!ccd) {  // C^{kb}_{ij} enters only through P_ab sum_k C t_k^a
     Scope sc(h, "cterm");
     auto Cp = view(w.Cp, {Po, v, o});
-    contract(s, "bkx,px->pbk", MONE, view(w.Vvovv_p, {v, o, Pv}), taup, false, Cp);
+    contract(s, "bkx,px->pbk", MONE, view(w.Vvovv_p, {v, o, Pv}), taup, false, Cp, df_kind);
     k_expand_c<R>(w.Vooov, w.Cp, w.Cf, o, v, s);
     auto Cf = view(w.Cf, {o, o, v, o});
     // P^-_ij sum_c <bk||ci> t_j^c with <bk||ci> = (bc|ki) - (bi|kc):
@@ -1050,15 +1053,18 @@ static void reset_diis(Handle& h) {
 
 // ------------------------------------------------------------------ perturbative triples
 // E(+T) and E((T)) of App. C at the current amplitudes (FP64).  The excitation
-// elements <ab||ie> = (ai|be) - (ae|bi) are built once from the DF factors for every
-// occupied i ([i][a][b][e], o v^3).  Then for each occupied pair j<k and a batch of
-// i<j (the paper's unique triples, batched over i)
+// elements <ab||ie> = (ai|be) - (ae|bi) are built from the DF factors for the occupied i
+// of the resident blocks, packed over a<b ([i][(a<b)][e]).  Then for each occupied pair
+// j<k and a batch of i<j (the paper's unique triples, batched over i)
 //   W[i][a][b][c] = sum_e (<ab||ie> t_jk^ec + <ab||je> t_ki^ec + <ab||ke> t_ij^ec)
 //                 + sum_m (<am||ij> t_km^bc + <am||jk> t_im^bc + <am||ki> t_jm^bc)
-// (six GETTs; <am||xy> = -conj(<xy||ma>) from the stored ooov class), and the energy
-// kernel forms the cyclic sums W~, Z~, Y~ and the three energy terms of each triple,
-// reduced in a fixed order.  The host sums the triples in order:
-// E = (1/6) sum_{i<j<k} sum_{abc} (the (1/36) sum over all ijk, abc).
+// (<am||xy> = -conj(<xy||ma>) from the stored ooov class).  The sum over e is
+// antisymmetric in (a, b) and the sum over m in (b, c), so the two parts are formed
+// packed, We[i][(a<b)][c] and Wm[i][a][(b<c)]: half the o^3 v^4 and o^4 v^3 work of the
+// full W, in six GETTs.  The energy kernel forms the cyclic sums W~, Z~, Y~ from the two
+// packed parts and the three energy terms of each triple, reduced in a fixed order.  The
+// host sums the triples in order: E = (1/6) sum_{i<j<k} sum_{abc} (the (1/36) sum over
+// all ijk, abc).
 static void triples_impl(Handle& h, double* e4_out, double* e5_out, double* ey_out) {
   if (h.phase32)
     raise(EXACC_ERR_INVALID_ARG,
@@ -1070,67 +1076,81 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out, double* ey_o
   if (o < 3 || v < 3) return;
   if (h.op.triples_occ_block < 0) raise(EXACC_ERR_INVALID_ARG, "triples_occ_block < 0");
   const hipStream_t s = h.s;
-  const int64_t vv = (int64_t)v * v, v3 = vv * v, ooo = (int64_t)o * o * o;
+  const int64_t vv = (int64_t)v * v, ooo = (int64_t)o * o * o, Pv = h.P.Pv, pvv = Pv * v;
   const int nblk = triples_blocks(v);
   size_t free_b = 0, total_b = 0;
   HIPCHECK(hipMemGetInfo(&free_b, &total_b));
   const size_t small = (size_t)(2 * ooo + 2 * (int64_t)(o - 2) * nblk + 4) * 16 + (256u << 20);
-  const size_t row = (size_t)v3 * 16;
+  const size_t trow = (size_t)pvv * 16;   // packed tile of one occupied i
+  const size_t wrow = 2 * trow;           // We and Wm of one triple
   // occupied block size n_red: all of nocc when its tiles fit beside one W row, else the
   // largest with three blocks of tiles resident (or the requested size)
   int red = o;
-  if (small + (size_t)o * row + row > free_b) {
-    if (small + 4 * row > free_b)
+  if (small + (size_t)o * trow + wrow > free_b) {
+    if (small + 3 * trow + wrow > free_b)
       raise(EXACC_ERR_NOMEM, "triples: three <ab||ie> tile rows and one W row do not fit in free device memory");
-    red = (int)std::min<int64_t>(o, (int64_t)((free_b - small - row) / (3 * row)));
+    red = (int)std::min<int64_t>(o, (int64_t)((free_b - small - wrow) / (3 * trow)));
   }
   if (h.op.triples_occ_block > 0) red = std::min(red, h.op.triples_occ_block);
   const int nb_occ = (o + red - 1) / red;
   const int slots = nb_occ == 1 ? 1 : 3;
-  const size_t tiles = (size_t)slots * red * row;
-  if (small + tiles + row > free_b)
+  const size_t tiles = (size_t)slots * red * trow;
+  if (small + tiles + wrow > free_b)
     raise(EXACC_ERR_NOMEM, "triples: the <ab||ie> tiles of three occupied blocks do not fit; lower triples_occ_block");
   // W rows (one per triple of a batch): what fits beside the tiles, at most n_red
   const int64_t cap = std::max<int64_t>(
-      1, std::min<int64_t>(std::min(red, o - 2), (int64_t)((free_b - small - tiles) / 2 / row)));
+      1, std::min<int64_t>(std::min(red, o - 2), (int64_t)((free_b - small - tiles) / 2 / wrow)));
   h.use();
-  double* Ve = h.dalloc((int64_t)slots * red * v3);
-  double* W = h.dalloc(cap * v3);
+  double* Ve = h.dalloc((int64_t)slots * red * pvv);
+  double* We = h.dalloc(cap * pvv);
+  double* Wm = h.dalloc(cap * pvv);
   double* part = h.dalloc(2 * cap * nblk);  // 4 doubles per block
   double* tri = h.dalloc(2 * ooo);           // (e4, e5, ey, -) at [i][j][k]
   struct Free {
     Handle& h;
-    double** p[4];
+    double** p[5];
     ~Free() {
       for (auto q : p) h.dfree(*q);
     }
-  } fr{h, {&Ve, &W, &part, &tri}};
-  // full t2 [i][j][a][b] into H4 (an FP64 work array rebuilt every iteration)
+  } fr{h, {&Ve, &We, &Wm, &part, &tri}};
+  // full t2 [i][j][a][b] into H4 and t2 packed over the virtual pair [k][m][(b<c)] into
+  // TAU (FP64 work arrays rebuilt every iteration)
   k_unpack_full(h.x, h.x + 2 * (int64_t)o * v, nullptr, h.H4, o, v, s);
+  double* T2 = h.H4;
+  double* T2pv = h.TAU;
+  k_pack_last2<double>(T2pv, T2, nullptr, (int64_t)o * o, v, vv, s);
   Views<double> b = bviews(h, h.Bt);
   const int64_t nX = (int64_t)h.P.n * X;
-  // tiles <ab||ie> = (ai|be) - (ae|bi) of occupied block q into slot sl, [i][a][b][e]:
-  // e contiguous, so the W GETTs read both operands along K
+  // tiles <ab||ie> = (ai|be) - (ae|bi), a<b, of occupied block q into slot sl,
+  // [i][(a<b)][e]: per a, the rows b > a; e contiguous, so the W GETTs read both operands
+  // along K
   int held[3] = {-1, -1, -1};
   auto build = [&](int q, int sl) {
     if (held[sl] == q) return;
     const int i0 = q * red, ni = std::min(red, o - i0);
-    auto VeV = view(Ve + 2 * (int64_t)sl * red * v3, {ni, v, v, v});
-    auto Bvo_q = sview(b.Bvo.p + 2 * (int64_t)i0 * X, {v, ni, X}, {nX, X, 1});
-    contract(s, "aiP,beP->iabe", ONE, Bvo_q, b.Bvv, false, VeV);
-    contract(s, "aeP,biP->iabe", MONE, b.Bvv, Bvo_q, true, VeV);
+    double* tq = Ve + 2 * (int64_t)sl * red * pvv;
+    for (int a = 0; a + 1 < v; ++a) {
+      const int nb = v - a - 1;
+      const int64_t off = (int64_t)a * v - (int64_t)a * (a + 1) / 2;  // first pair (a, a+1)
+      auto Cv = sview(tq + 2 * off * v, {ni, nb, v}, {pvv, (int64_t)v, 1});
+      auto Bvo_a = sview(b.Bvo.p + 2 * ((int64_t)a * nX + (int64_t)i0 * X), {ni, X}, {X, 1});
+      auto Bvv_b = sview(b.Bvv.p + 2 * (int64_t)(a + 1) * nX, {nb, v, X}, {nX, X, 1});
+      contract(s, "beP,iP->ibe", ONE, Bvv_b, Bvo_a, false, Cv);
+      auto Bvv_a = sview(b.Bvv.p + 2 * (int64_t)a * nX, {v, X}, {X, 1});
+      auto Bvo_b = sview(b.Bvo.p + 2 * ((int64_t)(a + 1) * nX + (int64_t)i0 * X), {nb, ni, X}, {nX, X, 1});
+      contract(s, "eP,biP->ibe", MONE, Bvv_a, Bvo_b, true, Cv);
+    }
     held[sl] = q;
   };
   int slot_of[3] = {0, 0, 0};  // slot holding the tiles of the current K, J, I blocks
   auto tile = [&](int i, int which) {
-    return Ve + 2 * ((int64_t)slot_of[which] * red + (i - (i / red) * red)) * v3;
+    return Ve + 2 * ((int64_t)slot_of[which] * red + (i - (i / red) * red)) * pvv;
   };
-  double* T2 = h.H4;
-  const int64_t ovv = (int64_t)o * vv, oov = (int64_t)o * o * v, ov = (int64_t)o * v;
-  auto Vsl = [&](double* p) { return sview(p, {v, v, v}, {vv, (int64_t)v, 1}); };
+  const int64_t ovv = (int64_t)o * vv, oov = (int64_t)o * o * v, ov = (int64_t)o * v, opv = (int64_t)o * Pv;
   // t_jk^{ce} as [c][e] (e contiguous); t_jk^{ec} = -t_jk^{ce}
   auto Tpair = [&](int j, int k) { return sview(T2 + 2 * ((int64_t)j * o + k) * vv, {v, v}, {(int64_t)v, 1}); };
-  auto Tone = [&](int k) { return sview(T2 + 2 * (int64_t)k * ovv, {o, v, v}, {vv, (int64_t)v, 1}); };
+  // t_km^{(b<c)} as [m][(b<c)]
+  auto Tpv = [&](int k) { return sview(T2pv + 2 * (int64_t)k * opv, {o, Pv}, {Pv, 1}); };
   auto Vm = [&](int i, int j) {  // <ij||ma> as [m][a]; the terms use -conj of it
     return conj(sview(h.Vooov + 2 * ((int64_t)i * o + j) * ov, {o, v}, {(int64_t)v, 1}));
   };
@@ -1165,28 +1185,30 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out, double* ey_o
             const int i_hi = std::min(j, std::min(o, (bi + 1) * red));
             for (int i0 = bi * red; i0 < i_hi; i0 += (int)cap) {
               const int ni = (int)std::min<int64_t>(cap, i_hi - i0);
-              auto Wv = view(W, {ni, v, v, v});
+              auto Wev = view(We, {ni, Pv, v});
+              auto Wmv = view(Wm, {ni, v, Pv});
+              auto Vt3 = [&](double* p) { return sview(p, {Pv, v}, {(int64_t)v, 1}); };
               // sum_e <ab||ie> t_jk^ec = -sum_e <ab||ie> t_jk^ce, i over the batch
-              contract(s, "iabe,ce->iabc", MONE, sview(tile(i0, 2), {ni, v, v, v}, {v3, vv, (int64_t)v, 1}),
-                       Tpair(j, k), false, Wv);
+              contract(s, "ixe,ce->ixc", MONE, sview(tile(i0, 2), {ni, Pv, v}, {pvv, (int64_t)v, 1}),
+                       Tpair(j, k), false, Wev);
               // sum_e <ab||je> t_ki^ec, t_ki^ce = T2[k][i][c][e]
-              contract(s, "abe,ice->iabc", MONE, Vsl(tile(j, 1)),
-                       sview(T2 + 2 * ((int64_t)k * o + i0) * vv, {ni, v, v}, {vv, (int64_t)v, 1}), true, Wv);
+              contract(s, "xe,ice->ixc", MONE, Vt3(tile(j, 1)),
+                       sview(T2 + 2 * ((int64_t)k * o + i0) * vv, {ni, v, v}, {vv, (int64_t)v, 1}), true, Wev);
               // sum_e <ab||ke> t_ij^ec, t_ij^ce = T2[i][j][c][e]
-              contract(s, "abe,ice->iabc", MONE, Vsl(tile(k, 0)),
-                       sview(T2 + 2 * ((int64_t)i0 * o + j) * vv, {ni, v, v}, {ovv, (int64_t)v, 1}), true, Wv);
-              // sum_m <am||ij> t_km^bc
-              contract(s, "ima,mbc->iabc", MONE,
+              contract(s, "xe,ice->ixc", MONE, Vt3(tile(k, 0)),
+                       sview(T2 + 2 * ((int64_t)i0 * o + j) * vv, {ni, v, v}, {ovv, (int64_t)v, 1}), true, Wev);
+              // sum_m <am||ij> t_km^bc, b<c
+              contract(s, "ima,my->iay", MONE,
                        conj(sview(h.Vooov + 2 * ((int64_t)i0 * o + j) * ov, {ni, o, v}, {oov, (int64_t)v, 1})),
-                       Tone(k), true, Wv);
+                       Tpv(k), false, Wmv);
               // sum_m <am||jk> t_im^bc
-              contract(s, "ma,imbc->iabc", MONE, Vm(j, k),
-                       sview(T2 + 2 * (int64_t)i0 * ovv, {ni, o, v, v}, {ovv, vv, (int64_t)v, 1}), true, Wv);
+              contract(s, "ma,imy->iay", MONE, Vm(j, k),
+                       sview(T2pv + 2 * (int64_t)i0 * opv, {ni, o, Pv}, {opv, Pv, 1}), true, Wmv);
               // sum_m <am||ki> t_jm^bc
-              contract(s, "ima,mbc->iabc", MONE,
+              contract(s, "ima,my->iay", MONE,
                        conj(sview(h.Vooov + 2 * ((int64_t)k * o + i0) * ov, {ni, o, v}, {ov, (int64_t)v, 1})),
-                       Tone(j), true, Wv);
-              k_triples_energy(W, h.Voovv, T2, h.x, h.eps, i0, ni, j, k, o, v, part, nblk, tri, s);
+                       Tpv(j), true, Wmv);
+              k_triples_energy(We, Wm, h.Voovv, T2, h.x, h.eps, i0, ni, j, k, o, v, part, nblk, tri, s);
             }
           }
         }

@@ -39,10 +39,12 @@ SAMPLE_SEED, SAMPLE_RANDOM, SAMPLE_TOP = 2024, 1_000_000, 500_000
 
 
 def triples_flops(o, v, X):
-    """Algorithmic flops of exacc_ccsd_triples: the <ab||ie> tiles (2 o v^3 X complex
-    multiply-adds) and, per occupied triple, 3 v^4 + 3 o v^3 (8 flops each)."""
+    """Algorithmic flops of exacc_ccsd_triples: the <ab||ie> tiles packed over a<b
+    (2 o P_v v X complex multiply-adds) and, per occupied triple, the two packed parts of W,
+    3 P_v v^2 (sum over e, a<b) + 3 o v P_v (sum over m, b<c), 8 flops each."""
     ntrip = o * (o - 1) * (o - 2) / 6
-    return 8.0 * (2.0 * o * v ** 3 * X + ntrip * (3.0 * v ** 4 + 3.0 * o * v ** 3))
+    Pv = v * (v - 1) / 2
+    return 8.0 * (2.0 * o * Pv * v * X + ntrip * (3.0 * Pv * v * v + 3.0 * o * v * Pv))
 
 
 def solve(eps_d, B_d, nocc, mode, tol, diis, max_iter, log, time_limit=None, triples=False,

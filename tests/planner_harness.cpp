@@ -415,28 +415,40 @@ int main() {
       run("cP,bdP->cbd", ONE, Ba, Bb, false, mk({v, nb, v}));
     }
   }
-  // perturbative triples: tiles of an occupied block and the W contractions of a batch
+  // perturbative triples: packed tiles of an occupied block (per a, rows b > a) and the
+  // contractions of a batch into the packed parts We[i][(a<b)][c] and Wm[i][a][(b<c)]
   {
-    const int64_t vv = (int64_t)v * v, v3 = vv * v, ovv = (int64_t)o * vv, ov = (int64_t)o * v,
-                  oov = (int64_t)o * o * v;
+    const int64_t vv = (int64_t)v * v, ov = (int64_t)o * v, oov = (int64_t)o * o * v,
+                  ovv = (int64_t)o * vv, pvv = Pv * v, opv = (int64_t)o * Pv;
     const int i0 = 1, ni = 2, j = 2, k = 2;
-    auto Ve = mk({3, v, v, v});
-    auto VeV = view(Ve.p, {ni, v, v, v});
-    auto Bvo_q = sview(Bvo.p + 2 * (int64_t)i0 * X, {v, ni, X}, {nX, X, 1});
-    run("aiP,beP->iabe", ONE, Bvo_q, Bvv, false, VeV);
-    run("aeP,biP->iabe", MONE, Bvv, Bvo_q, true, VeV);
+    auto Ve = mk({3, Pv, v});
+    for (int a = 0; a + 1 < v; ++a) {
+      const int nb = v - a - 1;
+      const int64_t off = (int64_t)a * v - (int64_t)a * (a + 1) / 2;
+      auto Cv = sview(Ve.p + 2 * off * v, {ni, nb, v}, {pvv, (int64_t)v, 1});
+      auto Bvo_a = sview(Bvo.p + 2 * ((int64_t)a * nX + (int64_t)i0 * X), {ni, X}, {X, 1});
+      auto Bvv_b = sview(Bvv.p + 2 * (int64_t)(a + 1) * nX, {nb, v, X}, {nX, X, 1});
+      run("beP,iP->ibe", ONE, Bvv_b, Bvo_a, false, Cv);
+      auto Bvv_a = sview(Bvv.p + 2 * (int64_t)a * nX, {v, X}, {X, 1});
+      auto Bvo_b = sview(Bvo.p + 2 * ((int64_t)(a + 1) * nX + (int64_t)i0 * X), {nb, ni, X}, {nX, X, 1});
+      run("eP,biP->ibe", MONE, Bvv_a, Bvo_b, true, Cv);
+    }
     auto T2f = mk({o, o, v, v});
-    auto W = mk({ni, v, v, v});
-    run("iabe,ce->iabc", MONE, sview(Ve.p, {ni, v, v, v}, {v3, vv, (int64_t)v, 1}),
-        sview(T2f.p + 2 * ((int64_t)1 * o + k) * vv, {v, v}, {(int64_t)v, 1}), false, W);
-    run("abe,ice->iabc", MONE, sview(Ve.p + 2 * v3, {v, v, v}, {vv, (int64_t)v, 1}),
-        sview(T2f.p + 2 * ((int64_t)k * o + 0) * vv, {ni, v, v}, {vv, (int64_t)v, 1}), true, W);
-    run("abe,ice->iabc", MONE, sview(Ve.p, {v, v, v}, {vv, (int64_t)v, 1}),
-        sview(T2f.p + 2 * ((int64_t)0 * o + j) * vv, {ni, v, v}, {ovv, (int64_t)v, 1}), true, W);
-    run("ima,mbc->iabc", MONE, conj(sview(Vooov.p + 2 * ((int64_t)0 * o + j) * ov, {ni, o, v}, {oov, (int64_t)v, 1})),
-        sview(T2f.p + 2 * (int64_t)k * ovv, {o, v, v}, {vv, (int64_t)v, 1}), true, W);
-    run("ma,imbc->iabc", MONE, conj(sview(Vooov.p + 2 * ((int64_t)1 * o + 2) * ov, {o, v}, {(int64_t)v, 1})),
-        sview(T2f.p, {ni, o, v, v}, {ovv, vv, (int64_t)v, 1}), true, W);
+    auto T2pv = mk({o, o, Pv});
+    auto We = mk({ni, Pv, v});
+    auto Wm = mk({ni, v, Pv});
+    run("ixe,ce->ixc", MONE, sview(Ve.p, {ni, Pv, v}, {pvv, (int64_t)v, 1}),
+        sview(T2f.p + 2 * ((int64_t)j * o + k) * vv, {v, v}, {(int64_t)v, 1}), false, We);
+    run("xe,ice->ixc", MONE, sview(Ve.p + 2 * pvv, {Pv, v}, {(int64_t)v, 1}),
+        sview(T2f.p + 2 * ((int64_t)k * o + 0) * vv, {ni, v, v}, {vv, (int64_t)v, 1}), true, We);
+    run("xe,ice->ixc", MONE, sview(Ve.p, {Pv, v}, {(int64_t)v, 1}),
+        sview(T2f.p + 2 * ((int64_t)0 * o + j) * vv, {ni, v, v}, {ovv, (int64_t)v, 1}), true, We);
+    run("ima,my->iay", MONE, conj(sview(Vooov.p + 2 * ((int64_t)0 * o + j) * ov, {ni, o, v}, {oov, (int64_t)v, 1})),
+        sview(T2pv.p + 2 * (int64_t)k * opv, {o, Pv}, {Pv, 1}), false, Wm);
+    run("ma,imy->iay", MONE, conj(sview(Vooov.p + 2 * ((int64_t)1 * o + 2) * ov, {o, v}, {(int64_t)v, 1})),
+        sview(T2pv.p, {ni, o, Pv}, {opv, Pv, 1}), true, Wm);
+    run("ima,my->iay", MONE, conj(sview(Vooov.p + 2 * ((int64_t)k * o + 0) * ov, {ni, o, v}, {ov, (int64_t)v, 1})),
+        sview(T2pv.p + 2 * (int64_t)j * opv, {o, Pv}, {Pv, 1}), true, Wm);
   }
   // DF factors: transform and metric GEMMs, the Newton-Schulz product
   {
