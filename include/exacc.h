@@ -79,12 +79,16 @@ typedef struct {
                                 largest that fits in free device memory (all of nocc if possible) */
   int    ladder_defect_correction; /* mixed precision, default 1: after the switch to FP64, one
                                 FP64 iteration stores the particle-ladder product L(tau_ref) of its
-                                amplitudes; the iterations that follow form every term in FP64 except
-                                the ladder, taken as L(tau_ref) + L_low(tau - tau_ref) with L_low in
-                                the low precision of the mode (its error shrinks with tau - tau_ref),
-                                until ||Delta|| <= tol or 4 of them bring no new lowest ||Delta||;
-                                then at least fp64_final_iters full FP64 iterations.  0: full FP64
-                                iterations from the switch on */
+                                amplitudes (and, where the reference arrays fit in the budget and
+                                in device memory, its ring product H_ref Tq_ref and H_ref); the
+                                iterations that follow form every other term in FP64 and take the
+                                ladder as L(tau_ref) + L_low(tau - tau_ref) and the ring as
+                                H_ref Tq_ref + [H_ref dTq + dH Tq]_low, the bracketed products in
+                                the low precision of the mode on differences formed in FP64 (their
+                                rounding is relative to the differences), until ||Delta|| <= tol
+                                or 4 of them bring no new lowest ||Delta||; then at least
+                                fp64_final_iters full FP64 iterations.  0: full FP64 iterations
+                                from the switch on */
 } exacc_ccsd_opts;
 
 /* Fill *o with the defaults listed above. */
@@ -92,7 +96,11 @@ void exacc_ccsd_default_opts(exacc_ccsd_opts* o);
 
 /* Device bytes create() will allocate for this problem (the a-priori memory
  * footprint the paper reports in "Coupled cluster implementation").
- * opts may be NULL (defaults).  Returns 0 for invalid sizes. */
+ * opts may be NULL (defaults).  Returns 0 for invalid sizes.  In the mixed
+ * modes the estimate includes the reference arrays of the ring correction
+ * (ladder_defect_correction) when they fit in hbm_budget_bytes (or no budget is
+ * set); create drops them when the plan with them exceeds the device memory, and
+ * the estimate then overstates the footprint by that part. */
 size_t exacc_ccsd_memory_estimate(int nocc, int nvir, int naux, const exacc_ccsd_opts* opts);
 
 /* Validate the inputs, copy them to the device, build the stored integral

@@ -87,8 +87,10 @@ void k_pack_last2(T* out, const T* in, const int* rowmap, int64_t rows, int m, i
 template <typename T>
 void k_unpack_tau(const double* t1, const double* t2p, T* T2, T* TAU, T* taup, int o, int v,
                   hipStream_t s);
+// Tq[b][j][k][c] = T2[j][k][c][b], Xp = Tq / 2 + t1[k][b] t1[j][c] (- t1r[k][b] t1r[j][c])
 template <typename T>
-void k_ring_operands(const T* T2, const double* t1, T* Tq, T* Xp, int o, int v, hipStream_t s);
+void k_ring_operands(const T* T2, const double* t1, T* Tq, T* Xp, int o, int v, hipStream_t s,
+                     const double* t1r = nullptr);
 template <typename T>
 void k_expand_c(const T* Vooov, const T* Cp, T* Cf, int o, int v, hipStream_t s);
 // W[b'][(c<d)] = Ta[c][b'][d] - Ta[d][b'][c] over c, d < v, rows of W ldw apart
@@ -150,5 +152,9 @@ void k_unpack_full(const double* t1, const double* t2p, double* t1_out, double* 
                    int v, hipStream_t s);
 void k_pack_amplitudes(const double* t1, const double* t2, double* x, int o, int v,
                        hipStream_t s);
+// t2_out [o][o][v][v] FP32 = the full antisymmetric t2p - r2p (packed inputs, FP64 difference)
+void k_unpack_diff(const double* t2p, const double* r2p, float* t2_out, int o, int v, hipStream_t s);
+// out = a - b (FP64), nreal reals
+void k_sub(const double* a, const double* b, double* out, int64_t nreal, hipStream_t s);
 
 }  // namespace exacc

@@ -167,9 +167,11 @@ __global__ void unpack_tau_kernel(const double* __restrict__ t1, const double* _
 }
 
 // Tq[b][j][k][c] = T2[j][k][c][b];  Xp[b][j][k][c] = 1/2 Tq + t1[k][b] t1[j][c]
+// (- t1r[k][b] t1r[j][c] when t1r is given: the operands of a difference T2 - T2_ref)
 template <typename T>
 __global__ void ring_operands_kernel(const T* __restrict__ T2, const double* __restrict__ t1,
-                                     T* __restrict__ Tq, T* __restrict__ Xp, int o, int v) {
+                                     T* __restrict__ Tq, T* __restrict__ Xp, int o, int v,
+                                     const double* __restrict__ t1r) {
   __shared__ double tr[32][33], ti[32][33];
   const int b0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
   const int64_t jk = blockIdx.z;
@@ -191,7 +193,9 @@ __global__ void ring_operands_kernel(const T* __restrict__ T2, const double* __r
       const z q{tr[tx][r], ti[tx][r]};
       const int64_t off = ((int64_t)b * oo + jk) * v + c;
       st(Tq, off, q);
-      st(Xp, off, add(scal(0.5, q), mul(ld(t1, (int64_t)k * v + b), ld(t1, (int64_t)j * v + c))));
+      z p = mul(ld(t1, (int64_t)k * v + b), ld(t1, (int64_t)j * v + c));
+      if (t1r) p = sub(p, mul(ld(t1r, (int64_t)k * v + b), ld(t1r, (int64_t)j * v + c)));
+      st(Xp, off, add(scal(0.5, q), p));
     }
   }
 }
@@ -485,6 +489,34 @@ __global__ void unpack_full_kernel(const double* __restrict__ t2p, double* __res
   }
 }
 
+// t2[i][j][a][b] = FP32 of the full antisymmetric t2 - t2_ref, from their packed forms
+// (the difference is formed in FP64)
+__global__ void unpack_diff_kernel(const double* __restrict__ t2p, const double* __restrict__ r2p,
+                                   float* __restrict__ t2, int o, int v) {
+  const int64_t vv = (int64_t)v * v, tot = (int64_t)o * o * vv, Pv = (int64_t)v * (v - 1) / 2;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int64_t ij = t / vv, ab = t - ij * vv;
+    const int i = (int)(ij / o), j = (int)(ij - (int64_t)i * o);
+    const int a = (int)(ab / v), b = (int)(ab - (int64_t)a * v);
+    z val{0, 0};
+    if (i != j && a != b) {
+      const int pi = i < j ? i : j, pj = i < j ? j : i;
+      const int pa = a < b ? a : b, pb = a < b ? b : a;
+      const double sg = ((i < j) == (a < b)) ? 1.0 : -1.0;
+      const int64_t q = pidx(pi, pj, o) * Pv + pidx(pa, pb, v);
+      val = scal(sg, sub(ld(t2p, q), ld(r2p, q)));
+    }
+    st(t2, t, val);
+  }
+}
+
+// out = a - b, n reals
+__global__ void sub_kernel(const double* __restrict__ a, const double* __restrict__ b,
+                           double* __restrict__ out, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB)
+    out[t] = a[t] - b[t];
+}
+
 __global__ void pack_amp_kernel(const double* __restrict__ t2, double* __restrict__ x2, int o,
                                 int v) {
   const int64_t Po = (int64_t)o * (o - 1) / 2, Pv = (int64_t)v * (v - 1) / 2, tot = Po * Pv;
@@ -623,11 +655,12 @@ void k_unpack_tau(const double* t1, const double* t2p, T* T2, T* TAU, T* taup, i
 }
 
 template <typename T>
-void k_ring_operands(const T* T2, const double* t1, T* Tq, T* Xp, int o, int v, hipStream_t s) {
+void k_ring_operands(const T* T2, const double* t1, T* Tq, T* Xp, int o, int v, hipStream_t s,
+                     const double* t1r) {
   const int64_t oo = (int64_t)o * o;
   if (oo > 65535) raise(-5, "nocc too large for ring operand permute");
   dim3 grid((v + 31) / 32, (v + 31) / 32, (unsigned)oo), block(32, 8);
-  hipLaunchKernelGGL(ring_operands_kernel<T>, grid, block, 0, s, T2, t1, Tq, Xp, o, v);
+  hipLaunchKernelGGL(ring_operands_kernel<T>, grid, block, 0, s, T2, t1, Tq, Xp, o, v, t1r);
   HIPCHECK(hipGetLastError());
 }
 
@@ -933,6 +966,19 @@ void k_unpack_full(const double* t1, const double* t2p, double* t1_out, double* 
   HIPCHECK(hipGetLastError());
 }
 
+void k_unpack_diff(const double* t2p, const double* r2p, float* t2_out, int o, int v, hipStream_t s) {
+  const int64_t tot = (int64_t)o * o * v * v;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(unpack_diff_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, t2p, r2p, t2_out, o, v);
+  HIPCHECK(hipGetLastError());
+}
+
+void k_sub(const double* a, const double* b, double* out, int64_t nreal, hipStream_t s) {
+  if (nreal <= 0) return;
+  hipLaunchKernelGGL(sub_kernel, dim3(nblocks(nreal)), dim3(TB), 0, s, a, b, out, nreal);
+  HIPCHECK(hipGetLastError());
+}
+
 void k_pack_amplitudes(const double* t1, const double* t2, double* x, int o, int v, hipStream_t s) {
   (void)t1;
   const int64_t tot = ((int64_t)o * (o - 1) / 2) * ((int64_t)v * (v - 1) / 2);
@@ -944,7 +990,8 @@ void k_pack_amplitudes(const double* t1, const double* t2, double* x, int o, int
 #define EXACC_INST(T)                                                                          \
   template void k_pack_last2<T>(T*, const T*, const int*, int64_t, int, int64_t, hipStream_t);   \
   template void k_unpack_tau<T>(const double*, const double*, T*, T*, T*, int, int, hipStream_t); \
-  template void k_ring_operands<T>(const T*, const double*, T*, T*, int, int, hipStream_t);      \
+  template void k_ring_operands<T>(const T*, const double*, T*, T*, int, int, hipStream_t,       \
+                                   const double*);                                               \
   template void k_expand_c<T>(const T*, const T*, T*, int, int, hipStream_t);                    \
   template void k_ladder_antisym<T>(const T*, T*, int, int, int64_t, hipStream_t);               \
   template void k_transpose_tail<T>(const T*, int64_t, int64_t, int64_t, int64_t, T*, int64_t,       \

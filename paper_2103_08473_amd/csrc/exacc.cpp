@@ -55,6 +55,9 @@ struct Plan {
   };
   std::vector<Item> items;
   size_t bytes_persistent = 0, bytes_peak = 0;
+  // the defect-corrected phase also covers the ring (its reference arrays are planned in)
+  bool ring_dc = false;
+  size_t bytes_peak_no_ring_dc = 0;
 };
 
 static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
@@ -106,10 +109,24 @@ static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
                         ? 2 * B16(p.Po * p.Pv) +
                               (op.precision == EXACC_MIXED_BF16X3 ? bvs : B16(n * n * X) / 2)
                         : 0;
+  // ring part of the defect correction: the reference amplitudes, the FP64 reference ring
+  // product, FP32 copies of the reference intermediate H and of the correction dH, the kept
+  // FP32 <kl||cd>, and the DF t1 intermediates of the amplitude difference
+  const size_t ring_dc = dc ? B16(p.L) + B16(p.oovv) + B16(p.oovv) + B16(p.oovv) / 2 +
+                                  B16(oo * X + (int64_t)v * o * X + (int64_t)o * v)
+                            : 0;
   const size_t phase64 = common + big64 + vovv_tmp + dc;
   const size_t phase32 = common + big32;
   p.bytes_persistent = mixed ? phase32 : common + big64;
   p.bytes_peak = std::max(create_peak, mixed ? std::max(phase32, phase64) : phase64);
+  p.bytes_peak_no_ring_dc = p.bytes_peak;
+  if (ring_dc) {
+    const size_t with = std::max(p.bytes_peak, phase64 + ring_dc);
+    if (op.hbm_budget_bytes == 0 || with <= op.hbm_budget_bytes) {
+      p.ring_dc = true;
+      p.bytes_peak = with;
+    }
+  }
   return p;
 }
 
@@ -172,6 +189,11 @@ struct Handle {
   double best_dc = -1.0;
   int since_best_dc = 0;
   double *tau_ref = nullptr, *Zref = nullptr;
+  // ring part (plan.ring_dc): x_ref = amplitudes of the reference iteration, Rref = its
+  // FP64 ring product H Tq, Href32 = FP32 H, D32 = FP32 correction dH; Ud, Vtd, t1d: the DF
+  // t1 intermediates and t1 of the amplitude difference
+  double *x_ref = nullptr, *Rref = nullptr, *Ud = nullptr, *Vtd = nullptr, *t1d = nullptr;
+  float *Href32 = nullptr, *D32 = nullptr;
   // Lambda equations (App. D): buffers allocated on first use.  prepared: the
   // similarity-transformed Hamiltonian pieces (H4 = W_ovvo as [b][j][m][e], Cf = W_ovoo,
   // Ap = W_oooo packed, Gac/Gki/Hkc = F_vv/-F_oo/F_ov, Wooov, the dressed factor Bd) were
@@ -387,7 +409,7 @@ static void ensure_fp64_classes(Handle& h, bool keep_low_ladder = false) {
   if (!keep_low_ladder || h.Bvs) h.dfree(h.Bt32);
   h.dfree(h.Voooo32);
   h.dfree(h.Vooov32);
-  h.dfree(h.Voovv32);
+  if (!keep_low_ladder || !h.P.ring_dc) h.dfree(h.Voovv32);
   h.dfree(h.Vvovv_p32);
   h.Voovv = h.dalloc(h.P.oovv);
   build_oovv(h, h.Voovv);
@@ -555,6 +577,64 @@ static void ladder_apply_herm(Handle& h, const Work<R>& w, const R* F, int64_t r
   }
 }
 
+// The ring term of the FP64 iterations after a mixed-precision switch (when its reference
+// arrays fit): with H = H^{ak}_{ci}, Tq the permuted T2 and the reference point of the
+// first FP64 iteration (x_ref, Rref = H_ref Tq_ref, Href32),
+//   H Tq = Rref + H_ref dTq + dH Tq,   dH = H1(dt1) + dXp <kl||cd>,
+// exactly, where d = current - reference, H1 the t1-linear DF terms of H and Xp the
+// ring operand (t2 / 2 + t1 t1): the differences are formed in FP64 from the amplitudes,
+// the three o^3 v^3 products run in the low precision of the mode (their rounding is
+// relative to the small differences), the t1-linear DF part of dH in FP64.  Scratch: Z
+// and H4 as FP32 halves (dT2 then Tq; dTq, dXp), Xp for dH in FP64 before it takes R.
+static void ring_defect_corrected(Handle& h, const Work<double>& w, const Views<double>& b, bool ccd) {
+  const int o = h.P.o, v = h.P.v, X = h.P.X;
+  const hipStream_t s = h.s;
+  const int64_t ov = (int64_t)o * v, oovv = h.P.oovv;
+  const int rk = h.op.precision == EXACC_MIXED_BF16X3 ? GETT_RING_BF16X3 : GETT_RING;
+  float* Za = reinterpret_cast<float*>(w.Z);
+  float* Zb = Za + 2 * oovv;
+  float* Ha = reinterpret_cast<float*>(w.H4);
+  float* Hb = Ha + 2 * oovv;
+  {
+    Scope sc(h, "ring_dc");
+    k_sub(h.x, h.x_ref, h.t1d, 2 * ov, s);
+    k_unpack_diff(h.x + 2 * ov, h.x_ref + 2 * ov, Za, o, v, s);
+    k_ring_operands<float>(Za, h.x, Ha, Hb, o, v, s, h.x_ref);  // dTq, dXp
+    k_cast(w.Tq, Za, 2 * oovv, s);                               // Tq in FP32
+  }
+  if (!ccd) {
+    Scope sc(h, "ring_dc");
+    auto t1d = view(h.t1d, {o, v});
+    auto Ud = view(h.Ud, {o, o, X});
+    auto Vtd = view(h.Vtd, {v, o, X});
+    auto Hd = view(w.Xp, {v, o, o, v});
+    contract(s, "kdP,id->kiP", ONE, b.Bov, t1d, false, Ud);
+    contract(s, "acP,ic->aiP", ONE, b.Bvv, t1d, false, Vtd);
+    contract(s, "acP,kiP->aikc", ONE, b.Bvv, Ud, false, Hd);
+    contract(s, "aiP,kcP->aikc", MONE, Vtd, b.Bov, true, Hd);
+    contract(s, "klic,la->aikc", MONE, view(w.Vooov, {o, o, o, v}), t1d, true, Hd);
+    k_cast(w.Xp, h.D32, 2 * oovv, s);
+  } else {
+    dzero(h, h.D32, oovv);
+  }
+  {
+    Scope sc(h, "ring_build");
+    const int64_t o_vv = (int64_t)o * v * v;
+    auto V32 = sview(h.Voovv32, {o, o, v, v}, {o_vv, (int64_t)v, ov, 1});
+    contract(s, "aild,klcd->aikc", ONE, view(Hb, {v, o, o, v}), V32, true, view(h.D32, {v, o, o, v}), rk);
+  }
+  {
+    Scope sc(h, "ring");
+    auto Rl = view(Zb, {o, o, v, v});
+    contract(s, "aikc,bjkc->ijab", ONE, view(h.Href32, {v, o, o, v}), view(Ha, {v, o, o, v}), false, Rl, rk);
+    contract(s, "aikc,bjkc->ijab", ONE, view(h.D32, {v, o, o, v}), view(Za, {v, o, o, v}), true, Rl, rk);
+    dzero(h, w.R_, oovv);
+    k_add2(w.R_, h.Rref, Zb, 2 * oovv, s);
+    if (!ccd)
+      contract(s, "aiP,bjP->ijab", ONE, view(w.Vt, {v, o, X}), b.Bvo, true, view(w.R_, {o, o, v, v}));
+  }
+}
+
 // The particle ladder of the FP64 iterations after a mixed-precision switch.  dc = 1: the
 // full FP64 product at the current amplitudes, kept as Zref = L(tau_ref) with tau_ref.
 // dc = 2: L(tau) = L(tau_ref) + L(tau - tau_ref), the second product in the mode's low
@@ -692,6 +772,14 @@ static void compute_residual(Handle& h) {
     return;
   }
   auto H4 = view(w.H4, {v, o, o, v});
+  bool ring_done = false;
+  if constexpr (sizeof(R) == sizeof(double)) {
+    if (h.dc == 2 && h.P.ring_dc) {
+      ring_defect_corrected(h, w, b, ccd);
+      ring_done = true;
+    }
+  }
+  if (!ring_done) {
   {
     Scope sc(h, "ring_build");
     // <ak||ci> = (ac|ki) - (ai|kc), formed from the factors each iteration
@@ -708,7 +796,15 @@ static void compute_residual(Handle& h) {
   {
     Scope sc(h, "ring");
     contract(s, "aikc,bjkc->ijab", ONE, H4, view(w.Tq, {v, o, o, v}), false, Rv, ring_kind);
+    if constexpr (sizeof(R) == sizeof(double)) {
+      if (h.dc == 1 && h.P.ring_dc) {  // reference point of the corrected ring
+        dcopy(h, h.Rref, w.R_, h.P.oovv);
+        k_cast(w.H4, h.Href32, 2 * h.P.oovv, s);
+        dcopy(h, h.x_ref, h.x, h.P.L);
+      }
+    }
     if (!ccd) contract(s, "aiP,bjP->ijab", ONE, Vt, b.Bvo, true, Rv, df_kind);
+  }
   }
   // Z and its views with i<->j or a<->b swapped: a term X launched into Z and,
   // negated, into a swapped view accumulates P^-_ij X (or P^-_ab X) directly
@@ -977,6 +1073,14 @@ static void end_defect_correction(Handle& h) {
   h.dfree(h.Zref);
   h.dfree(h.Bvs);
   h.dfree(h.Bt32);
+  h.dfree(h.x_ref);
+  h.dfree(h.Rref);
+  h.dfree(h.Href32);
+  h.dfree(h.D32);
+  h.dfree(h.Ud);
+  h.dfree(h.Vtd);
+  h.dfree(h.t1d);
+  h.dfree(h.Voovv32);
 }
 
 static double one_iteration(Handle& h) {
@@ -1022,6 +1126,16 @@ static double one_iteration(Handle& h) {
     if (dc) {
       h.tau_ref = h.dalloc(h.P.Po * h.P.Pv);
       h.Zref = h.dalloc(h.P.Po * h.P.Pv);
+      if (h.P.ring_dc) {
+        const int o = h.P.o, v = h.P.v, X = h.P.X;
+        h.x_ref = h.dalloc(h.P.L);
+        h.Rref = h.dalloc(h.P.oovv);
+        h.Href32 = reinterpret_cast<float*>(h.dalloc((h.P.oovv + 1) / 2));
+        h.D32 = reinterpret_cast<float*>(h.dalloc((h.P.oovv + 1) / 2));
+        h.Ud = h.dalloc((int64_t)o * o * X);
+        h.Vtd = h.dalloc((int64_t)v * o * X);
+        h.t1d = h.dalloc((int64_t)o * v);
+      }
       h.dc = 1;
     }
     HIPCHECK(hipStreamSynchronize(h.s));
@@ -1577,6 +1691,14 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
   Plan P = make_plan(o, v, X, op);
   if (op.hbm_budget_bytes && P.bytes_peak > op.hbm_budget_bytes)
     raise(EXACC_ERR_NOMEM, "memory plan exceeds hbm_budget_bytes");
+  if (P.ring_dc) {  // the ring part of the defect correction only where its arrays fit
+    size_t fr = 0, tot = 0;
+    HIPCHECK(hipMemGetInfo(&fr, &tot));
+    if (P.bytes_peak + ((size_t)4 << 30) > tot) {
+      P.ring_dc = false;
+      P.bytes_peak = P.bytes_peak_no_ring_dc;
+    }
+  }
   Handle* h = new Handle();
   try {
     h->P = P;
