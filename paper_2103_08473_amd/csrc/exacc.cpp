@@ -32,7 +32,10 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
   if (e == hipSuccess) return;
   char buf[512];
   snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
-  if (e == hipErrorOutOfMemory) raise(EXACC_ERR_NOMEM, buf);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();  // a failed allocation leaves the device usable
+    raise(EXACC_ERR_NOMEM, buf);
+  }
   raise(EXACC_ERR_DEVICE, buf);
 }
 
@@ -258,6 +261,16 @@ struct Handle {
     return (double*)p;
   }
 };
+
+// Calls after create that allocate on top of the handle (the Lambda buffers, the triples
+// temporaries) stay within opts.hbm_budget_bytes together with what the handle holds.
+static void check_budget(const Handle& h, size_t extra, const char* what) {
+  if (!h.op.hbm_budget_bytes) return;
+  size_t held = 0;
+  for (const AllocRange& r : h.ranges) held += r.bytes;
+  if (held + extra > h.op.hbm_budget_bytes)
+    raise(EXACC_ERR_NOMEM, std::string(what) + " would exceed hbm_budget_bytes");
+}
 
 struct Scope {  // event-bracketed stage (only with opts.timing)
   Handle& h;
@@ -1215,18 +1228,23 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out, double* ey_o
   const int64_t cap = std::max<int64_t>(
       1, std::min<int64_t>(std::min(red, o - 2), (int64_t)((free_b - small - tiles) / 2 / wrow)));
   h.use();
-  double* Ve = h.dalloc((int64_t)slots * red * pvv);
-  double* We = h.dalloc(cap * pvv);
-  double* Wm = h.dalloc(cap * pvv);
-  double* part = h.dalloc(2 * cap * nblk);  // 4 doubles per block
-  double* tri = h.dalloc(2 * ooo);           // (e4, e5, ey, -) at [i][j][k]
-  struct Free {
+  check_budget(h, tiles + (size_t)cap * wrow + (size_t)(4 * cap * nblk + 4 * ooo) * 8, "triples temporaries");
+  double *Ve = nullptr, *We = nullptr, *Wm = nullptr, *part = nullptr, *tri = nullptr;
+  struct Free {  // released on every exit, a failed allocation included
     Handle& h;
     double** p[5];
     ~Free() {
-      for (auto q : p) h.dfree(*q);
+      for (auto q : p) try {
+          h.dfree(*q);
+        } catch (...) {
+        }
     }
   } fr{h, {&Ve, &We, &Wm, &part, &tri}};
+  Ve = h.dalloc((int64_t)slots * red * pvv);
+  We = h.dalloc(cap * pvv);
+  Wm = h.dalloc(cap * pvv);
+  part = h.dalloc(2 * cap * nblk);  // 4 doubles per block
+  tri = h.dalloc(2 * ooo);          // (e4, e5, ey, -) at [i][j][k]
   // full t2 [i][j][a][b] into H4 and t2 packed over the virtual pair [k][m][(b<c)] into
   // TAU (FP64 work arrays rebuilt every iteration)
   k_unpack_full(h.x, h.x + 2 * (int64_t)o * v, nullptr, h.H4, o, v, s);
@@ -1370,8 +1388,24 @@ static void lambda_alloc(Handle& h) {
   size_t fr = 0, tot = 0;
   HIPCHECK(hipMemGetInfo(&fr, &tot));
   if ((size_t)need * 16 + (256u << 20) > fr) raise(EXACC_ERR_NOMEM, "Lambda buffers do not fit");
-  // into a local set first: the handle records them only once every allocation succeeded
+  check_budget(h, (size_t)need * 16, "Lambda buffers");
+  // into a local set first: the handle records them only once every allocation succeeded;
+  // on a failed allocation the ones already made are released before the error propagates
   Handle::Lam L;
+  struct Undo {
+    Handle& h;
+    Handle::Lam& L;
+    bool armed = true;
+    ~Undo() {
+      if (!armed) return;
+      for (double** q : {&L.l1w, &L.s1, &L.gt, &L.Lq, &L.Z1, &L.Bd, &L.Wooov, &L.O3a, &L.O3b, &L.LTp,
+                         &L.Q1, &L.gP, &L.gam, &L.lam})
+        try {
+          h.dfree(*q);
+        } catch (...) {
+        }
+    }
+  } undo{h, L};
   L.l1w = h.dalloc(o * v);
   L.s1 = h.dalloc(o * v);
   L.gt = h.dalloc(o * v);
@@ -1387,6 +1421,7 @@ static void lambda_alloc(Handle& h) {
   L.gam = h.dalloc((o + v) * (o + v));
   L.lam = h.dalloc(h.P.L);
   dzero(h, L.lam, h.P.L);
+  undo.armed = false;
   h.lam = L;
 }
 

@@ -107,3 +107,27 @@ def test_lambda_rejects_other_methods_and_low_precision(lib):
         with pytest.raises(exacc.ExaccError) as e:
             cc.lambda_iterate(1)
         assert e.value.status == exacc.ERR_INVALID_ARG
+
+
+def test_later_allocations_respect_the_budget(lib):
+    """The Lambda buffers are allocated after create: with the budget set to the create plan
+    (nocc=12, nvir=14: the buffers, about 2.4 MB, exceed the plan's 0.8 MB of create-time
+    temporaries) they are refused with NOMEM, nothing stays allocated and the handle keeps
+    iterating; with twice the plan the Lambda step and the triples run."""
+    from paper_2103_08473_amd import exacc
+    from paper_2103_08473_amd.exacc import CCSD
+    o, v, X = 12, 14, 42
+    eps, B = make_system(o, v, X, seed=5)
+    plan = exacc.memory_estimate(o, v, X)
+    with CCSD(eps, B, o, hbm_budget_bytes=plan, tol=1e-10) as cc:
+        cc.solve(max_iter=40)
+        for _ in range(2):   # a second attempt is refused the same way (nothing leaked)
+            with pytest.raises(exacc.ExaccError) as e:
+                cc.lambda_iterate(1)
+            assert e.value.status == exacc.ERR_NOMEM
+        st, _, r, _ = cc.iterate(1)
+        assert np.isfinite(r)
+    with CCSD(eps, B, o, hbm_budget_bytes=2 * plan, tol=1e-10) as cc:
+        cc.solve(max_iter=40)
+        cc.lambda_iterate(1)
+        assert all(np.isfinite(x) for x in cc.triples())
