@@ -1723,21 +1723,29 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
   if (op.cc2 && op.doubles_only) raise(EXACC_ERR_INVALID_ARG, "cc2 and doubles_only are exclusive");
   if (!(op.tol >= 0) || !std::isfinite(op.level_shift))
     raise(EXACC_ERR_INVALID_ARG, "bad tol or level_shift");
-  Plan P = make_plan(o, v, X, op);
-  if (op.hbm_budget_bytes && P.bytes_peak > op.hbm_budget_bytes)
-    raise(EXACC_ERR_NOMEM, "memory plan exceeds hbm_budget_bytes");
-  if (P.ring_dc) {  // the ring part of the defect correction only where its arrays fit
+  exacc_ccsd_opts opx = op;
+  Plan P = make_plan(o, v, X, opx);
+  if (opx.precision != EXACC_FP64 && opx.ladder_defect_correction) {
+    // the defect correction's reference arrays only where they fit in the device memory
+    // (4 GiB kept free): first without the ring part, then without any
     size_t fr = 0, tot = 0;
     HIPCHECK(hipMemGetInfo(&fr, &tot));
-    if (P.bytes_peak + ((size_t)4 << 30) > tot) {
+    const size_t keep = (size_t)4 << 30;
+    if (P.ring_dc && P.bytes_peak + keep > tot) {
       P.ring_dc = false;
       P.bytes_peak = P.bytes_peak_no_ring_dc;
     }
+    if (P.bytes_peak + keep > tot) {
+      opx.ladder_defect_correction = 0;
+      P = make_plan(o, v, X, opx);
+    }
   }
+  if (op.hbm_budget_bytes && P.bytes_peak > op.hbm_budget_bytes)
+    raise(EXACC_ERR_NOMEM, "memory plan exceeds hbm_budget_bytes");
   Handle* h = new Handle();
   try {
     h->P = P;
-    h->op = op;
+    h->op = opx;
     h->tm.on = op.timing != 0;
     if (op.stream) {
       h->s = (hipStream_t)op.stream;
