@@ -82,8 +82,9 @@ typedef struct {
                                 amplitudes (and, where the reference arrays fit in the budget and
                                 in device memory, its ring product H_ref Tq_ref and H_ref); the
                                 iterations that follow form every other term in FP64 and take the
-                                ladder as L(tau_ref) + L_low(tau - tau_ref) and the ring as
-                                H_ref Tq_ref + [H_ref dTq + dH Tq]_low, the bracketed products in
+                                ladder as L(tau_ref) + L_low(tau - tau_ref), the ring as
+                                H_ref Tq_ref + [H_ref dTq + dH Tq]_low and (with the ring part) the
+                                vovv.tau product of C^{kb}_{ij} likewise, the bracketed products in
                                 the low precision of the mode on differences formed in FP64 (their
                                 rounding is relative to the differences), until ||Delta|| <= tol
                                 or 4 of them bring no new lowest ||Delta||; then at least

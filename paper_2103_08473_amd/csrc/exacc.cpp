@@ -114,9 +114,11 @@ static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
                         : 0;
   // ring part of the defect correction: the reference amplitudes, the FP64 reference ring
   // product, FP32 copies of the reference intermediate H and of the correction dH, the kept
-  // FP32 <kl||cd>, and the DF t1 intermediates of the amplitude difference
+  // FP32 <kl||cd>, the DF t1 intermediates of the amplitude difference; and for the vovv.tau
+  // product of C^{kb}_{ij} the kept FP32 vovv class and the FP64 reference product
   const size_t ring_dc = dc ? B16(p.L) + B16(p.oovv) + B16(p.oovv) + B16(p.oovv) / 2 +
-                                  B16(oo * X + (int64_t)v * o * X + (int64_t)o * v)
+                                  B16(oo * X + (int64_t)v * o * X + (int64_t)o * v) +
+                                  B16((int64_t)v * o * p.Pv) / 2 + B16(p.Po * v * o)
                             : 0;
   const size_t phase64 = common + big64 + vovv_tmp + dc;
   const size_t phase32 = common + big32;
@@ -196,6 +198,7 @@ struct Handle {
   // FP64 ring product H Tq, Href32 = FP32 H, D32 = FP32 correction dH; Ud, Vtd, t1d: the DF
   // t1 intermediates and t1 of the amplitude difference
   double *x_ref = nullptr, *Rref = nullptr, *Ud = nullptr, *Vtd = nullptr, *t1d = nullptr;
+  double* Cref = nullptr;  // reference vovv.tau product of C^{kb}_{ij}, [(i<j)][b][k]
   float *Href32 = nullptr, *D32 = nullptr;
   // Lambda equations (App. D): buffers allocated on first use.  prepared: the
   // similarity-transformed Hamiltonian pieces (H4 = W_ovvo as [b][j][m][e], Cf = W_ovoo,
@@ -423,7 +426,7 @@ static void ensure_fp64_classes(Handle& h, bool keep_low_ladder = false) {
   h.dfree(h.Voooo32);
   h.dfree(h.Vooov32);
   if (!keep_low_ladder || !h.P.ring_dc) h.dfree(h.Voovv32);
-  h.dfree(h.Vvovv_p32);
+  if (!keep_low_ladder || !h.P.ring_dc) h.dfree(h.Vvovv_p32);
   h.Voovv = h.dalloc(h.P.oovv);
   build_oovv(h, h.Voovv);
   h.Vvovv_p = h.dalloc((int64_t)h.P.v * h.P.o * h.P.Pv);
@@ -835,7 +838,25 @@ static void compute_residual(Handle& h) {
   if (!ccd) {  // C^{kb}_{ij} enters only through P_ab sum_k C t_k^a
     Scope sc(h, "cterm");
     auto Cp = view(w.Cp, {Po, v, o});
-    contract(s, "bkx,px->pbk", MONE, view(w.Vvovv_p, {v, o, Pv}), taup, false, Cp, df_kind);
+    bool cdone = false;
+    if constexpr (sizeof(R) == sizeof(double)) {
+      if (h.P.ring_dc && h.dc == 2) {  // Cp = Cp(tau_ref) - vovv_low . (tau - tau_ref)_low
+        const int64_t np = Po * Pv, nc = Po * v * o;
+        float* dtau = reinterpret_cast<float*>(w.H4);
+        float* C32 = dtau + 2 * h.P.oovv;
+        k_diff_cast(w.taup, h.tau_ref, dtau, 2 * np, s);
+        const int ck = h.op.precision == EXACC_MIXED_BF16X3 ? GETT_RING_BF16X3 : GETT_GENERIC;
+        contract(s, "bkx,px->pbk", MONE, view(h.Vvovv_p32, {v, o, Pv}), view(dtau, {Po, Pv}), false,
+                 view(C32, {Po, v, o}), ck);
+        dzero(h, w.Cp, nc);
+        k_add2(w.Cp, h.Cref, C32, 2 * nc, s);
+        cdone = true;
+      }
+    }
+    if (!cdone) contract(s, "bkx,px->pbk", MONE, view(w.Vvovv_p, {v, o, Pv}), taup, false, Cp, df_kind);
+    if constexpr (sizeof(R) == sizeof(double)) {
+      if (h.P.ring_dc && h.dc == 1) dcopy(h, h.Cref, w.Cp, Po * v * o);
+    }
     k_expand_c<R>(w.Vooov, w.Cp, w.Cf, o, v, s);
     auto Cf = view(w.Cf, {o, o, v, o});
     // P^-_ij sum_c <bk||ci> t_j^c with <bk||ci> = (bc|ki) - (bi|kc):
@@ -1093,7 +1114,9 @@ static void end_defect_correction(Handle& h) {
   h.dfree(h.Ud);
   h.dfree(h.Vtd);
   h.dfree(h.t1d);
+  h.dfree(h.Cref);
   h.dfree(h.Voovv32);
+  h.dfree(h.Vvovv_p32);
 }
 
 static double one_iteration(Handle& h) {
@@ -1148,6 +1171,7 @@ static double one_iteration(Handle& h) {
         h.Ud = h.dalloc((int64_t)o * o * X);
         h.Vtd = h.dalloc((int64_t)v * o * X);
         h.t1d = h.dalloc((int64_t)o * v);
+        h.Cref = h.dalloc(h.P.Po * v * o);
       }
       h.dc = 1;
     }
