@@ -209,6 +209,58 @@ def cpu_baseline(eps, B, o, budget_s=15.0):
                       "flops counted as the GPU ladder's algorithmic work for those rows" % (rows - 1, dt)}
 
 
+def oracle_iteration(eps, B, o, ladder_rows_sample=6):
+    """One-off timing of one oracle CCSD iteration on the host (CPU only).
+
+    Timed whole: the oracle's integral classes (build_integrals) and its residual with the
+    particle-ladder term set to zero (everything else of eq. CC_general), then the Jacobi
+    step.  The ladder term, which does not fit in one run at this size, is timed on
+    `ladder_rows_sample` of its rows a (each row builds <ab||cd> for all b, c, d and
+    contracts it with tau: the same work for every a) and scaled to all v rows."""
+    import numpy as np
+    import oracle.ccsd as occ
+    hi = host_info()
+    v = eps.size - o
+    out = {"host": hi, "workload": "nocc=%d nvir=%d naux=%d" % (o, v, B.shape[0])}
+
+    def say(msg):
+        print("oracle iteration: " + msg, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    ints = occ.build_integrals(B, o)
+    out["integrals_s"] = round(time.perf_counter() - t0, 2)
+    say("integrals %.1f s" % out["integrals_s"])
+    rng = np.random.default_rng(3)
+    t1 = 1e-3 * (rng.standard_normal((o, v)) + 1j * rng.standard_normal((o, v)))
+    t2 = 1e-3 * (rng.standard_normal((o, o, v, v)) + 1j * rng.standard_normal((o, o, v, v)))
+    t2 = t2 - t2.transpose(1, 0, 2, 3)
+    t2 = t2 - t2.transpose(0, 1, 3, 2)
+    full_ladder = occ._ladder
+    occ._ladder = lambda ints_, tau_: np.zeros(tau_.shape, dtype=np.complex128)
+    try:
+        t0 = time.perf_counter()
+        S1, S2 = occ.residual(eps, ints, t1, t2)
+        d1, d2 = occ.denominators(eps, o)
+        occ.jacobi_step(S1, S2, d1, d2)
+        out["residual_without_ladder_s"] = round(time.perf_counter() - t0, 2)
+    finally:
+        occ._ladder = full_ladder
+    say("residual without the ladder %.1f s" % out["residual_without_ladder_s"])
+    del S1, S2
+    tau = occ.tau(t1, t2)
+    rows = np.linspace(0, v - 1, ladder_rows_sample).astype(int)
+    t0 = time.perf_counter()
+    for a in rows:
+        occ.ladder_rows(ints["B"], o, tau, int(a), int(a) + 1)
+    per_row = (time.perf_counter() - t0) / len(rows)
+    out["ladder_rows_timed"] = [int(a) for a in rows]
+    out["ladder_s_per_row"] = round(per_row, 3)
+    out["ladder_s"] = round(per_row * v, 1)
+    say("ladder %.2f s per row, %.0f s for %d rows" % (per_row, per_row * v, v))
+    out["iteration_s"] = round(out["residual_without_ladder_s"] + out["ladder_s"], 1)
+    return out
+
+
 def solve_leg(exacc, eps_d, B_d, o, stream, precision, tol, max_iter, progress, steps=0, warmup=0,
               stop_after_timed=False):
     """One solve to convergence from create; optionally the `steps` iterations after
@@ -282,7 +334,16 @@ def main():
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="first run one plain device-to-device copy of this many GiB (a known-size "
                          "kernel to scale hardware byte counters by)")
+    ap.add_argument("--oracle-iteration", action="store_true",
+                    help="only time one iteration of the CPU oracle at the benchmark size (no GPU; "
+                         "about 10 minutes and 150 GB of host memory) and print it as JSON")
     args = ap.parse_args()
+    if args.oracle_iteration:
+        from paper_2103_08473_amd.synth import make_system
+        o = WORKLOAD["nocc"]
+        eps, B = make_system(o, WORKLOAD["nvir"], WORKLOAD["naux"], seed=WORKLOAD["seed"])
+        print(json.dumps(oracle_iteration(eps, B, o)), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)

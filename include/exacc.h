@@ -90,6 +90,12 @@ typedef struct {
                                 or 4 of them bring no new lowest ||Delta||; then at least
                                 fp64_final_iters full FP64 iterations.  0: full FP64 iterations
                                 from the switch on */
+  int    graph_residual;     /* 1: the residual computation of each iteration kind (low precision,
+                                FP64, FP64 with corrected products) is recorded into a HIP graph
+                                on its first iteration and replayed by one launch afterwards
+                                (results bitwise those of direct launches; for small problems,
+                                whose iterations are bound by per-kernel launch cost).  Ignored
+                                when timing is set.  Default 0 */
 } exacc_ccsd_opts;
 
 /* Fill *o with the defaults listed above. */

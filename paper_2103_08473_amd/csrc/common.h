@@ -116,6 +116,12 @@ void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipS
 // the packed parts We[y][(a<b)][c], Wm[y][a][(b<c)] of W and the full T2; written to
 // out[4 * (((i0 + y) * o + j) * o + k)]
 int triples_blocks(int v);
+// zero nbytes at p / copy nbytes from src to d (nbytes a multiple of 8, pointers 8-byte aligned)
+void k_zero_bytes(void* p, int64_t nbytes, hipStream_t s);
+void k_copy_bytes(void* d, const void* src, int64_t nbytes, hipStream_t s);
+// Acat[y][a][t][m] = conj(<x_t y_t||m a>), (x_0, y_0) = (k, i0 + y), (x_1, y_1) = (i0 + y, j)
+void k_triples_acat(const double* Vooov, int i0, int ni, int j, int k, int o, int v, double* out,
+                    hipStream_t s);
 void k_triples_energy(const double* We, const double* Wm, const double* Voovv, const double* T2,
                       const double* t1, const double* eps, int i0, int ni, int j, int k, int o, int v,
                       double* partial, int nblk, double* out, hipStream_t s);

@@ -795,9 +795,11 @@ __global__ void triples_energy_kernel(const double* __restrict__ Web, const doub
   }
   const int tc = tb + rem;
   const int a0 = 8 * ta, b0 = 8 * tb, c0 = 8 * tc;
-  // cube q at LDS index (x * 8 + y) * 8 + w holds its value for (a, b, c) = (a0+x, b0+y, c0+w);
+  // cube q at LDS index x * 73 + y * 9 + w holds its value for (a, b, c) = (a0+x, b0+y, c0+w)
+  // (pitches 73 and 9: the transposed stores of cubes 1, 2 and 5 fall in distinct banks);
   // entries whose pair is not p < q (unused by a < b < c) are zero
-  __shared__ double qr[6][512], qi[6][512];
+  constexpr int CQ = 8 * 73;
+  __shared__ double qr[6][CQ], qi[6][CQ];
   for (int e = threadIdx.x; e < 512; e += TB) {
     const int u = e >> 6, m = (e >> 3) & 7, f = e & 7;  // f fastest
     z g[6];
@@ -809,13 +811,13 @@ __global__ void triples_energy_kernel(const double* __restrict__ Web, const doub
       g[0] = (in && a < b) ? Ep(a, b, c) : z{0, 0};
       g[3] = (in && b < c) ? Mp(a, b, c) : z{0, 0};
       g[4] = (in && a < c) ? Mp(b, a, c) : z{0, 0};
-      at[0] = at[3] = at[4] = (u * 8 + m) * 8 + f;
+      at[0] = at[3] = at[4] = u * 73 + m * 9 + f;
     }
     // 1: We(bc, a), a fastest
     {
       const int b = b0 + u, c = c0 + m, a = a0 + f;
       g[1] = (a < v && b < v && c < v && b < c) ? Ep(b, c, a) : z{0, 0};
-      at[1] = (f * 8 + u) * 8 + m;
+      at[1] = f * 73 + u * 9 + m;
     }
     // 2: We(ac, b), b fastest;  5: Wm(c, ab), b fastest
     {
@@ -823,7 +825,7 @@ __global__ void triples_energy_kernel(const double* __restrict__ Web, const doub
       const bool in = a < v && b < v && c < v;
       g[2] = (in && a < c) ? Ep(a, c, b) : z{0, 0};
       g[5] = (in && a < b) ? Mp(c, a, b) : z{0, 0};
-      at[2] = at[5] = (u * 8 + f) * 8 + m;
+      at[2] = at[5] = u * 73 + f * 9 + m;
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -838,8 +840,9 @@ __global__ void triples_energy_kernel(const double* __restrict__ Web, const doub
     const int x = e >> 6, y = (e >> 3) & 7, w = e & 7;
     const int a = a0 + x, b = b0 + y, c = c0 + w;
     if (!(c < v && a < b && b < c)) continue;
-    const z wt{qr[0][e] + qr[1][e] - qr[2][e] + qr[3][e] - qr[4][e] + qr[5][e],
-               qi[0][e] + qi[1][e] - qi[2][e] + qi[3][e] - qi[4][e] + qi[5][e]};
+    const int q = x * 73 + y * 9 + w;
+    const z wt{qr[0][q] + qr[1][q] - qr[2][q] + qr[3][q] - qr[4][q] + qr[5][q],
+               qi[0][q] + qi[1][q] - qi[2][q] + qi[3][q] - qi[4][q] + qi[5][q]};
     const z zz = add(Zf(a, b, c), add(Zf(c, a, b), Zf(b, c, a)));
     const z yy = add(Yf(a, b, c), add(Yf(c, a, b), Yf(b, c, a)));
     const double D = eps[o + a] + eps[o + b] + eps[o + c] - eo;
@@ -865,6 +868,26 @@ __global__ void triples_energy_kernel(const double* __restrict__ Web, const doub
     part[4 * q] = s4[0];
     part[4 * q + 1] = s5[0];
     part[4 * q + 2] = sy[0];
+  }
+}
+
+// Acat[y][a][t][m] = conj(<x_t y_t||m a>) for the two sums over m of a triples batch whose
+// excitation elements depend on i = i0 + y: t = 0 -> <k i||m a>, t = 1 -> <i j||m a>
+// (Vooov [x][y][m][a])
+__global__ void triples_acat_kernel(const double* __restrict__ Vooov, int i0, int ni, int j, int k,
+                                    int o, int v, double* __restrict__ out) {
+  const int64_t tot = (int64_t)ni * v * 2 * o;
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
+    const int m = (int)(t % o);
+    int64_t r = t / o;
+    const int tt = (int)(r % 2);
+    r /= 2;
+    const int a = (int)(r % v);
+    const int y = (int)(r / v);
+    const int i = i0 + y;
+    const int x0 = tt == 0 ? k : i, y0 = tt == 0 ? i : j;
+    const z g = ld(Vooov, (((int64_t)x0 * o + y0) * o + m) * v + a);
+    st(out, t, z{g.x, -g.y});
   }
 }
 
@@ -898,6 +921,55 @@ __global__ void triples_reduce_kernel(const double* __restrict__ part, int nblk,
     out[4 * idx + 1] = s5[0];
     out[4 * idx + 2] = sy[0];
   }
+}
+
+// Fill and copy of nbytes (a multiple of 8) with 16-byte or 8-byte vector stores: the
+// stream-ordered zero and device-to-device copy of the iteration, as kernels so that a
+// captured iteration graph holds kernel nodes only.
+template <typename V>
+__global__ void fill_zero_kernel(V* __restrict__ p, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB) p[t] = V{};
+}
+template <typename V>
+__global__ void copy_words_kernel(V* __restrict__ d, const V* __restrict__ src, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB) d[t] = src[t];
+}
+
+void k_zero_bytes(void* p, int64_t nbytes, hipStream_t s) {
+  if (nbytes <= 0) return;
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  if (reinterpret_cast<uintptr_t>(p) % 16 == 0 && nbytes % 16 == 0) {
+    const int64_t n = nbytes / 16;
+    hipLaunchKernelGGL(fill_zero_kernel<u4>, dim3(nblocks(n)), dim3(TB), 0, s, (u4*)p, n);
+  } else {
+    const int64_t n = nbytes / 8;
+    hipLaunchKernelGGL(fill_zero_kernel<u2>, dim3(nblocks(n)), dim3(TB), 0, s, (u2*)p, n);
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+void k_copy_bytes(void* d, const void* src, int64_t nbytes, hipStream_t s) {
+  if (nbytes <= 0) return;
+  typedef unsigned u4 __attribute__((ext_vector_type(4)));
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  if (reinterpret_cast<uintptr_t>(d) % 16 == 0 && reinterpret_cast<uintptr_t>(src) % 16 == 0 &&
+      nbytes % 16 == 0) {
+    const int64_t n = nbytes / 16;
+    hipLaunchKernelGGL(copy_words_kernel<u4>, dim3(nblocks(n)), dim3(TB), 0, s, (u4*)d, (const u4*)src, n);
+  } else {
+    const int64_t n = nbytes / 8;
+    hipLaunchKernelGGL(copy_words_kernel<u2>, dim3(nblocks(n)), dim3(TB), 0, s, (u2*)d, (const u2*)src, n);
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+void k_triples_acat(const double* Vooov, int i0, int ni, int j, int k, int o, int v, double* out,
+                    hipStream_t s) {
+  const int64_t tot = (int64_t)ni * v * 2 * o;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(triples_acat_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, Vooov, i0, ni, j, k, o, v, out);
+  HIPCHECK(hipGetLastError());
 }
 
 int triples_blocks(int v) {

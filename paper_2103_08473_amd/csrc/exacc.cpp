@@ -222,10 +222,16 @@ struct Handle {
   int iters = 0;
   Timer tm;
 
+  // executable graphs of the residual computation (opts.graph_residual), one per iteration
+  // kind: 0 FP64, 1 low precision, 2 FP64 with the defect-corrected products
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+
   double* slot_x(int k) { return diis + (int64_t)2 * k * 2 * P.L; }
   double* slot_e(int k) { return diis + ((int64_t)2 * k + 1) * 2 * P.L; }
 
   ~Handle() {
+    for (auto& g : gexec)
+      if (g) (void)hipGraphExecDestroy(g);
     for (void* p : allocs) (void)hipFree(p);
     if (host) (void)hipHostFree(host);
     for (auto e : tm.pool) (void)hipEventDestroy(e);
@@ -352,15 +358,16 @@ static Views<R> bviews(Handle& h, R* Bt) {
   return w;
 }
 
+// Zero and copy inside the iteration run as kernels (a captured iteration graph then holds
+// kernel nodes only).
 template <typename R>
 static void dzero(Handle& h, R* dst, int64_t celems) {
-  if (celems > 0) HIPCHECK(hipMemsetAsync(dst, 0, celems * 2 * sizeof(R), h.s));
+  k_zero_bytes(dst, celems * 2 * (int64_t)sizeof(R), h.s);
 }
 
 template <typename R>
 static void dcopy(Handle& h, R* dst, const R* src, int64_t celems) {
-  if (celems > 0)
-    HIPCHECK(hipMemcpyAsync(dst, src, celems * 2 * sizeof(R), hipMemcpyDeviceToDevice, h.s));
+  k_copy_bytes(dst, src, celems * 2 * (int64_t)sizeof(R), h.s);
 }
 
 
@@ -1013,6 +1020,53 @@ static void compute_residual_phase(Handle& h) {
     compute_residual<double>(h);
 }
 
+// Release the graph of one iteration kind (its buffers are about to go, or it will not run
+// again).
+static void drop_graph(Handle& h, int kind) {
+  if (!h.gexec[kind]) return;
+  HIPCHECK(hipStreamSynchronize(h.s));
+  HIPCHECK(hipGraphExecDestroy(h.gexec[kind]));
+  h.gexec[kind] = nullptr;
+}
+
+// The residual computation of one iteration.  With opts.graph_residual the first iteration
+// of each kind records its kernels into a graph (stream capture: every launch, the
+// planner's included, is recorded, not run) and every iteration of that kind then replays
+// it with one launch: the same kernels with the same arguments in the same order, so the
+// results are bitwise those of the direct launches, without the host's per-kernel launch
+// and planning cost.  The captured kernels read and write only the handle's fixed buffers
+// (amplitudes, work arrays, stored classes); a kind's graph is released before any of its
+// buffers is (the switch, the end of the corrected phase).  The reference iteration of the
+// corrected phase runs once and is not captured; timed runs (opts.timing) are not captured.
+static void residual_step(Handle& h) {
+  const int kind = h.phase32 ? 1 : h.dc == 0 ? 0 : h.dc == 2 ? 2 : -1;
+  if (!h.op.graph_residual || h.tm.on || kind < 0) {
+    compute_residual_phase(h);
+    return;
+  }
+  if (!h.gexec[kind]) {
+    hipGraph_t g = nullptr;
+    HIPCHECK(hipStreamBeginCapture(h.s, hipStreamCaptureModeThreadLocal));
+    try {
+      compute_residual_phase(h);
+    } catch (...) {
+      hipGraph_t partial = nullptr;
+      (void)hipStreamEndCapture(h.s, &partial);
+      if (partial) (void)hipGraphDestroy(partial);
+      (void)hipGetLastError();
+      throw;
+    }
+    HIPCHECK(hipStreamEndCapture(h.s, &g));
+    const hipError_t e = hipGraphInstantiate(&h.gexec[kind], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      h.gexec[kind] = nullptr;
+      HIPCHECK(e);
+    }
+  }
+  HIPCHECK(hipGraphLaunch(h.gexec[kind], h.s));
+}
+
 // ------------------------------------------------------------------ one iteration
 static zc device_energy(Handle& h) {
   Scope sc(h, "energy");
@@ -1101,6 +1155,7 @@ static int diis_slot(Handle& h) {
 // product and the low-precision ladder operands are released.
 static void end_defect_correction(Handle& h) {
   HIPCHECK(hipStreamSynchronize(h.s));
+  drop_graph(h, 2);
   h.dc = 0;
   h.fp64_iters = 0;
   h.dfree(h.tau_ref);
@@ -1122,7 +1177,7 @@ static void end_defect_correction(Handle& h) {
 static double one_iteration(Handle& h) {
   const bool was32 = h.phase32;
   const int dc_now = h.dc;
-  compute_residual_phase(h);
+  residual_step(h);
   const int slot = diis_slot(h);
   double* xt = h.slot_x(slot);
   double* e = h.slot_e(slot);
@@ -1158,6 +1213,7 @@ static double one_iteration(Handle& h) {
   }
   if (was32 && (rnorm < h.op.mixed_switch_tol || h.since_best32 >= kStall)) {
     const bool dc = h.op.ladder_defect_correction != 0 && !h.op.cc2 && h.P.Po * h.P.Pv > 0;
+    drop_graph(h, 1);
     ensure_fp64_classes(h, dc);
     if (dc) {
       h.tau_ref = h.dalloc(h.P.Po * h.P.Pv);
@@ -1252,23 +1308,26 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out, double* ey_o
   const int64_t cap = std::max<int64_t>(
       1, std::min<int64_t>(std::min(red, o - 2), (int64_t)((free_b - small - tiles) / 2 / wrow)));
   h.use();
-  check_budget(h, tiles + (size_t)cap * wrow + (size_t)(4 * cap * nblk + 4 * ooo) * 8, "triples temporaries");
-  double *Ve = nullptr, *We = nullptr, *Wm = nullptr, *part = nullptr, *tri = nullptr;
+  check_budget(h, tiles + (size_t)cap * wrow + (size_t)(4 * cap * nblk + 4 * ooo) * 8 +
+                     (size_t)cap * v * 2 * o * 16,
+               "triples temporaries");
+  double *Ve = nullptr, *We = nullptr, *Wm = nullptr, *part = nullptr, *tri = nullptr, *Acat = nullptr;
   struct Free {  // released on every exit, a failed allocation included
     Handle& h;
-    double** p[5];
+    double** p[6];
     ~Free() {
       for (auto q : p) try {
           h.dfree(*q);
         } catch (...) {
         }
     }
-  } fr{h, {&Ve, &We, &Wm, &part, &tri}};
+  } fr{h, {&Ve, &We, &Wm, &part, &tri, &Acat}};
   Ve = h.dalloc((int64_t)slots * red * pvv);
   We = h.dalloc(cap * pvv);
   Wm = h.dalloc(cap * pvv);
   part = h.dalloc(2 * cap * nblk);  // 4 doubles per block
   tri = h.dalloc(2 * ooo);          // (e4, e5, ey, -) at [i][j][k]
+  Acat = h.dalloc(cap * v * 2 * o);
   // full t2 [i][j][a][b] into H4 and t2 packed over the virtual pair [k][m][(b<c)] into
   // TAU (FP64 work arrays rebuilt every iteration)
   k_unpack_full(h.x, h.x + 2 * (int64_t)o * v, nullptr, h.H4, o, v, s);
@@ -1353,17 +1412,16 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out, double* ey_o
               // sum_e <ab||ke> t_ij^ec, t_ij^ce = T2[i][j][c][e]
               contract(s, "xe,ice->ixc", MONE, Vt3(tile(k, 0)),
                        sview(T2 + 2 * ((int64_t)i0 * o + j) * vv, {ni, v, v}, {ovv, (int64_t)v, 1}), true, Wev);
-              // sum_m <am||ij> t_km^bc, b<c
-              contract(s, "ima,my->iay", MONE,
-                       conj(sview(h.Vooov + 2 * ((int64_t)i0 * o + j) * ov, {ni, o, v}, {oov, (int64_t)v, 1})),
-                       Tpv(k), false, Wmv);
+              // sum_m <am||ki> t_jm^bc + sum_m <am||ij> t_km^bc (b<c) as one product over
+              // K = (t, m), 2 nocc: the two excitation elements gathered into Acat[i][a][t][m],
+              // t_jm and t_km read as T2pv[j + t (k - j)]
+              k_triples_acat(h.Vooov, i0, ni, j, k, o, v, Acat, s);
+              contract(s, "iatm,tmy->iay", MONE, view(Acat, {ni, v, 2, o}),
+                       sview(T2pv + 2 * (int64_t)j * opv, {2, o, Pv}, {(int64_t)(k - j) * opv, Pv, 1}),
+                       false, Wmv);
               // sum_m <am||jk> t_im^bc
               contract(s, "ma,imy->iay", MONE, Vm(j, k),
                        sview(T2pv + 2 * (int64_t)i0 * opv, {ni, o, Pv}, {opv, Pv, 1}), true, Wmv);
-              // sum_m <am||ki> t_jm^bc
-              contract(s, "ima,my->iay", MONE,
-                       conj(sview(h.Vooov + 2 * ((int64_t)k * o + i0) * ov, {ni, o, v}, {ov, (int64_t)v, 1})),
-                       Tpv(j), true, Wmv);
               k_triples_energy(We, Wm, h.Voovv, T2, h.x, h.eps, i0, ni, j, k, o, v, part, nblk, tri, s);
             }
           }
@@ -1958,6 +2016,7 @@ void exacc_ccsd_default_opts(exacc_ccsd_opts* o) {
   o->cc2 = 0;
   o->mixed_switch_tol = 1e-5;
   o->ladder_defect_correction = 1;
+  o->graph_residual = 0;
 }
 
 size_t exacc_ccsd_memory_estimate(int nocc, int nvir, int naux, const exacc_ccsd_opts* opts) {

@@ -40,6 +40,7 @@ class Opts(ctypes.Structure):
         ("cc2", ctypes.c_int),
         ("triples_occ_block", ctypes.c_int),
         ("ladder_defect_correction", ctypes.c_int),
+        ("graph_residual", ctypes.c_int),
     ]
 
 

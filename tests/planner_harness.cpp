@@ -449,6 +449,12 @@ int main() {
         sview(T2pv.p, {ni, o, Pv}, {opv, Pv, 1}), true, Wm);
     run("ima,my->iay", MONE, conj(sview(Vooov.p + 2 * ((int64_t)k * o + 0) * ov, {ni, o, v}, {ov, (int64_t)v, 1})),
         sview(T2pv.p + 2 * (int64_t)j * opv, {o, Pv}, {Pv, 1}), true, Wm);
+    // the two sums over m fused over K = (t, m): t selects the amplitude row j1 or k1 > j1
+    const int j1 = 0, k1 = 2;
+    run("iatm,tmy->iay", MONE, mk({ni, v, 2, o}),
+        sview(T2pv.p + 2 * (int64_t)j1 * opv, {2, o, Pv}, {(int64_t)(k1 - j1) * opv, Pv, 1}), false, Wm);
+    run("iatm,tmy->iay", MONE, mk({ni, v, 2, o}),
+        sview(T2pv.p + 2 * (int64_t)1 * opv, {2, o, Pv}, {opv, Pv, 1}), true, Wm);
   }
   // DF factors: transform and metric GEMMs, the Newton-Schulz product
   {
