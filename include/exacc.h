@@ -96,6 +96,13 @@ typedef struct {
                                 (results bitwise those of direct launches; for small problems,
                                 whose iterations are bound by per-kernel launch cost).  Ignored
                                 when timing is set.  Default 0 */
+  int    ladder_group_nvir;  /* nvir up to which the particle ladder forms the integral tiles of
+                                all virtual rows in one product (3 kernel launches per
+                                iteration instead of about 2 nvir; v^4 naux complex
+                                multiply-adds instead of about v^4 naux / 4, and v^4 complex
+                                elements of scratch); requires the whole pair range in one
+                                ladder chunk (ladder_chunk_pairs 0 or >= P_v).  Default 64;
+                                0: per-row tiles at every size */
 } exacc_ccsd_opts;
 
 /* Fill *o with the defaults listed above. */

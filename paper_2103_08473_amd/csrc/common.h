@@ -96,6 +96,9 @@ void k_expand_c(const T* Vooov, const T* Cp, T* Cf, int o, int v, hipStream_t s)
 // W[b'][(c<d)] = Ta[c][b'][d] - Ta[d][b'][c] over c, d < v, rows of W ldw apart
 template <typename T>
 void k_ladder_antisym(const T* Ta, T* W, int nb, int v, int64_t ldw, hipStream_t s);
+// W[(a<b)][(c<d)] = Tf[a][c][b][d] - Tf[a][d][b][c] for all a < b (Tf: v^4, W: P_v x P_v)
+template <typename T>
+void k_ladder_antisym_all(const T* Tf, T* W, int v, hipStream_t s);
 // Wt[y][x] = W[x][col0 + y], x < rows, y < ncols (row strides ldw, ldt)
 template <typename T>
 void k_transpose_tail(const T* W, int64_t rows, int64_t ldw, int64_t col0, int64_t ncols, T* Wt,

@@ -262,6 +262,47 @@ __global__ void ladder_antisym_kernel(const T* __restrict__ Ta, T* __restrict__ 
   }
 }
 
+// All rows at once: W[(a<b)][(c<d)] = T[a][c][b][d] - T[a][d][b][c] from the full product
+// T[a][c][b][d] = sum_P F_ac F_bd (v^4 elements).  blockIdx.z = a, blockIdx.y = b - a - 1
+// (blocks past the row's last b exit), blockIdx.x = (c-tile <= d-tile) pair; the second T
+// tile is transposed through LDS as in ladder_antisym_kernel.
+template <typename T>
+__global__ void ladder_antisym_all_kernel(const T* __restrict__ Tf, T* __restrict__ W, int v) {
+  __shared__ double tr[32][33], ti[32][33];
+  const int a = blockIdx.z, b = a + 1 + (int)blockIdx.y;
+  if (b >= v) return;
+  const int ntile = (v + 31) / 32;
+  int tc = 0, rem = blockIdx.x;
+  while (rem >= ntile - tc) {
+    rem -= ntile - tc;
+    ++tc;
+  }
+  const int td = tc + rem;
+  const int c0 = 32 * tc, d0 = 32 * td;
+  const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+  const int64_t vv = (int64_t)v * v;
+  const T* Ta = Tf + 2 * ((int64_t)a * v * vv + (int64_t)b * v);  // [c][d] at c * v^2 + d
+  // stage T[a][d][b][c] for d in d-tile, c in c-tile (contiguous in c) as [c - c0][d - d0]
+  for (int r = ty; r < 32; r += 8) {
+    const int d = d0 + r, c = c0 + tx;
+    if (d < v && c < v) {
+      const z q = ld(Ta, (int64_t)d * vv + c);
+      tr[tx][r] = q.x;
+      ti[tx][r] = q.y;
+    }
+  }
+  __syncthreads();
+  const int64_t row = pidx(a, b, v), Pv = (int64_t)v * (v - 1) / 2;
+  for (int r = ty; r < 32; r += 8) {
+    const int c = c0 + r, d = d0 + tx;
+    if (c < v && d < v && c < d) {
+      const z p = ld(Ta, (int64_t)c * vv + d);
+      const z q{tr[r][tx], ti[r][tx]};
+      st(W, row * Pv + pidx(c, d, v), sub(p, q));
+    }
+  }
+}
+
 // Wt[y][x] = W[x][col0 + y] for x < rows, y < ncols (32 x 32 tiles through LDS: reads along
 // W rows and writes along Wt rows are both coalesced).
 template <typename T>
@@ -682,6 +723,16 @@ void k_ladder_antisym(const T* Ta, T* W, int nb, int v, int64_t ldw, hipStream_t
 }
 
 template <typename T>
+void k_ladder_antisym_all(const T* Tf, T* W, int v, hipStream_t s) {
+  if (v < 2) return;
+  const int nt = (v + 31) / 32;
+  if (v > 65535) raise(-5, "ladder too wide");
+  dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)(v - 1), (unsigned)(v - 1)), block(32, 8);
+  hipLaunchKernelGGL(ladder_antisym_all_kernel<T>, grid, block, 0, s, Tf, W, v);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename T>
 void k_transpose_tail(const T* W, int64_t rows, int64_t ldw, int64_t col0, int64_t ncols, T* Wt,
                       int64_t ldt, hipStream_t s) {
   if (rows <= 0 || ncols <= 0) return;
@@ -1066,6 +1117,7 @@ void k_pack_amplitudes(const double* t1, const double* t2, double* x, int o, int
                                    const double*);                                               \
   template void k_expand_c<T>(const T*, const T*, T*, int, int, hipStream_t);                    \
   template void k_ladder_antisym<T>(const T*, T*, int, int, int64_t, hipStream_t);               \
+  template void k_ladder_antisym_all<T>(const T*, T*, int, hipStream_t);                          \
   template void k_transpose_tail<T>(const T*, int64_t, int64_t, int64_t, int64_t, T*, int64_t,       \
                                     hipStream_t);                                                 \
   template void k_assemble_t2<T>(const T*, const T*, const T*, const double*, const double*,     \

@@ -48,6 +48,7 @@ struct Plan {
   int o, v, X, n;
   int64_t Po, Pv, L, vv, oovv;
   int64_t chunk_pairs;  // ladder W rows
+  bool ladder_grouped = false;  // all virtual rows of the ladder in one product (small nvir)
   int nslots;
   int64_t vovv_chunk;   // b values per vovv build step (create only)
   // complex-element counts
@@ -80,6 +81,7 @@ static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
   if (cp <= 0) cp = std::max<int64_t>(v, (int64_t)(2ll << 30) / rowbytes);
   cp = std::min<int64_t>(std::max<int64_t>(cp, std::max(1, v - 1)), std::max<int64_t>(1, p.Pv));
   p.chunk_pairs = cp;
+  p.ladder_grouped = v >= 2 && v <= op.ladder_group_nvir && cp == p.Pv;
   const int64_t vovv_row = (int64_t)o * v * v;  // per b
   p.vovv_chunk = std::max<int64_t>(1, std::min<int64_t>(v, (int64_t)(2ll << 30) / (16 * vovv_row)));
   const int64_t n = p.n, oo = (int64_t)o * o;
@@ -95,7 +97,7 @@ static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
                         + B16(2 * p.vv + 3 * oo + 3 * (int64_t)o * v + X + oo * X +
                               2 * (int64_t)v * o * X + p.Po * v * o + oo * v * o + oo * oo +
                               p.Po * p.Po)                       // small intermediates
-                        + B16((int64_t)v * std::max(1, v - 1) * v)  // Ta
+                        + B16(p.ladder_grouped ? p.vv * p.vv : (int64_t)v * std::max(1, v - 1) * v)  // Ta
                         + B16(p.chunk_pairs * std::max<int64_t>(1, p.Pv))  // W
                         + (256u << 20) + (2u << 20);             // split-K, reductions
   const size_t big64 = B16(p.oovv) + B16((int64_t)v * o * p.Pv);  // Voovv, Vvovv_p (FP64)
@@ -458,9 +460,41 @@ static void ensure_fp64_classes(Handle& h, bool keep_low_ladder = false) {
 template <typename R>
 static void ladder_apply_herm(Handle& h, const Work<R>& w, const R* F, int64_t row_stride,
                               const TV<R>& Lp, R* Znp, bool bf, bool use_bvs);
+// Small nvir (plan.ladder_grouped): all virtual rows in three launches instead of two per
+// row, the per-row products being too small to fill the chip.  T[a][c][b][d] = sum_P F_ac F_bd
+// over all a, b, c, d in one product (v^4 naux complex multiply-adds against the Hermitian
+// build's v^4 naux / 4, cheap at this size), W[(a<b)][(c<d)] = T[a][c][b][d] - T[a][d][b][c]
+// in one pass, then Znp += Lp W^T.  Needs no Hermitian factors.
+template <typename R>
+static void ladder_apply_grouped(Handle& h, const Work<R>& w, const R* F, int64_t row_stride,
+                                 const TV<R>& Lp, R* Znp, bool bf, bool use_bvs) {
+  const int v = h.P.v, X = h.P.X;
+  const int64_t Po = h.P.Po, Pv = h.P.Pv, vv = h.P.vv;
+  const hipStream_t s = h.s;
+  {
+    Scope sc(h, "ladder_build");
+    if (bf && use_bvs && h.Bvs) {  // pre-split rows (a, c), all v^2 of them contiguous
+      gemm_bf16x3_split(h.Bvs, h.Bvs, (int)vv, (int)vv, X, reinterpret_cast<float*>(w.Ta), vv, s);
+    } else {
+      auto Fv = sview(const_cast<R*>(F), {v, v, X}, {row_stride, X, 1});
+      contract(s, "acP,bdP->acbd", ONE, Fv, Fv, false, view(w.Ta, {v, v, v, v}),
+               bf ? GETT_LADDER_BUILD_BF16X3 : GETT_LADDER_BUILD);
+    }
+  }
+  {
+    Scope sc(h, "ladder_antisym");
+    k_ladder_antisym_all<R>(w.Ta, w.W, v, s);
+  }
+  Scope sc(h, "ladder_contract");
+  contract(s, "py,xy->px", ONE, Lp, view(w.W, {Pv, Pv}), true, sview(Znp, {Po, Pv}, {Pv, 1}),
+           bf ? GETT_LADDER_CONTRACT_BF16X3 : GETT_LADDER_CONTRACT);
+}
+
 template <typename R>
 static void ladder_apply(Handle& h, const Work<R>& w, const R* F, int64_t row_stride, const TV<R>& Lp,
                          R* Znp, bool bf, bool use_bvs, bool herm) {
+  if (h.P.ladder_grouped && h.P.Po > 0 && h.P.Pv > 0)
+    return ladder_apply_grouped<R>(h, w, F, row_stride, Lp, Znp, bf, use_bvs);
   if (herm) return ladder_apply_herm<R>(h, w, F, row_stride, Lp, Znp, bf, use_bvs);
   const int v = h.P.v, X = h.P.X;
   const int64_t Po = h.P.Po, Pv = h.P.Pv;
@@ -1963,7 +1997,7 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
     h->Cf = h->dalloc(oo * v * o);
     h->Af = h->dalloc(oo * oo);
     h->Ap = h->dalloc(P.Po * P.Po);
-    h->Ta = h->dalloc((int64_t)v * std::max(1, v - 1) * v);
+    h->Ta = h->dalloc(h->P.ladder_grouped ? h->P.vv * h->P.vv : (int64_t)v * std::max(1, v - 1) * v);
     h->W = h->dalloc(P.chunk_pairs * std::max<int64_t>(1, P.Pv));
     h->use();
     HIPCHECK(hipMemsetAsync(h->x, 0, P.L * 16, h->s));
@@ -2017,6 +2051,7 @@ void exacc_ccsd_default_opts(exacc_ccsd_opts* o) {
   o->mixed_switch_tol = 1e-5;
   o->ladder_defect_correction = 1;
   o->graph_residual = 0;
+  o->ladder_group_nvir = 64;
 }
 
 size_t exacc_ccsd_memory_estimate(int nocc, int nvir, int naux, const exacc_ccsd_opts* opts) {

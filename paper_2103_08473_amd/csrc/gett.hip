@@ -391,9 +391,14 @@ static void launch_cfg(const Gett<R>& g, hipStream_t s) {
     int nz = 1;
     h.kslice = g.K > 0 ? g.K : 1;
     const int64_t wgs = (int64_t)tiles * nb;
-    if (g_ws && wgs < 1024 && g.K >= 1024) {
-      int64_t want = (1024 + wgs - 1) / wgs;
-      want = want < (g.K + 255) / 256 ? want : (g.K + 255) / 256;  // >= 256 k per slice
+    // long K: slices of >= 256 k up to ~1024 workgroups; outputs of a few tiles (small
+    // problems, whose time is the serial k-loop of each workgroup): slices of >= 64 k up to
+    // ~256 workgroups
+    const bool long_k = wgs < 1024 && g.K >= 1024, few_tiles = wgs < 128 && g.K >= 128;
+    if (g_ws && (long_k || few_tiles)) {
+      int64_t want = long_k ? (1024 + wgs - 1) / wgs : (256 + wgs - 1) / wgs;
+      const int64_t kmin = long_k ? 256 : 64;
+      want = want < (g.K + kmin - 1) / kmin ? want : (g.K + kmin - 1) / kmin;
       const int64_t per = (int64_t)g.M * g.N * nb * 2 * (int64_t)sizeof(R);
       const int64_t cap = per > 0 ? (int64_t)(g_ws_bytes / per) : 0;
       if (want > cap) want = cap;

@@ -41,6 +41,7 @@ class Opts(ctypes.Structure):
         ("triples_occ_block", ctypes.c_int),
         ("ladder_defect_correction", ctypes.c_int),
         ("graph_residual", ctypes.c_int),
+        ("ladder_group_nvir", ctypes.c_int),
     ]
 
 

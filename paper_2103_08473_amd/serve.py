@@ -46,6 +46,7 @@ class Request:
     converged: bool = False
     status: int = 0
     mem: int = 0
+    mem_wait: bool = False   # was at the head of the queue with a slot free but not the memory
     error: str = ""
     inputs: object = field(default=None, repr=False)
 
@@ -112,6 +113,8 @@ class Server:
             self.in_use += req.mem
             req.admitted = self.now()
             self.pool.submit(self._run, req)
+        if self.queue and self.active < self.max_active:
+            self.queue[0].mem_wait = True
 
     def _run(self, req: Request):
         try:

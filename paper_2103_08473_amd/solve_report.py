@@ -177,6 +177,8 @@ def main():
                     help="occupied block size n_red of the triples loops (0: as large as fits)")
     ap.add_argument("--lambda", dest="lam", action="store_true",
                     help="after each solve, the Lambda equations (App. D) and the density (App. E)")
+    ap.add_argument("--ladder-group-nvir", type=int, default=None,
+                    help="opts.ladder_group_nvir (all ladder rows in one product up to this nvir)")
     ap.add_argument("--time-limit", type=float, default=None,
                     help="stop iterating once this many seconds have passed since start-up")
     args = ap.parse_args()
@@ -200,6 +202,8 @@ def main():
         extra = {} if args.switch_tol is None else {"mixed_switch_tol": args.switch_tol}
         if args.triples_block:
             extra["triples_occ_block"] = args.triples_block
+        if args.ladder_group_nvir is not None:
+            extra["ladder_group_nvir"] = args.ladder_group_nvir
         res, t1, t2 = solve(eps_d, B_d, o, mode, args.tol, args.diis, args.max_iter, log,
                             time_limit=args.time_limit, triples=args.triples, lam=args.lam, **extra)
         if args.ref:

@@ -27,16 +27,18 @@ LAMBDA_CASES = [(3, 4, 9), (5, 7, 13), (10, 40, 120), (12, 70, 150), (1, 9, 20),
                 (4, 1, 6)]
 
 
+@pytest.mark.parametrize("group", [64, 0])
 @pytest.mark.parametrize("o,v,X", LAMBDA_CASES)
-def test_lambda_residual_matches_oracle(lib, o, v, X):
-    """R1, R2 of App. D at random t and lambda, element by element, 1e-12 of max |R|."""
+def test_lambda_residual_matches_oracle(lib, o, v, X, group):
+    """R1, R2 of App. D at random t and lambda, element by element, 1e-12 of max |R|; the
+    ladder with all rows' tiles in one product (group 64) and per row (0)."""
     from paper_2103_08473_amd.exacc import CCSD
-    say("lambda residual case", o, v, X)
+    say("lambda residual case", o, v, X, "ladder_group_nvir", group)
     eps, B = make_system(o, v, X, seed=o * 1000 + v + 5, sigma=0.2)
     t1, t2 = make_amplitudes(o, v, seed=17 + o, scale=0.1)
     l1, l2 = make_amplitudes(o, v, seed=29 + o, scale=0.1)
     R1, R2 = lambda_residual(eps, _full_V(B, o + v), o, t1, t2, l1, l2)
-    with CCSD(eps, B, o) as cc:
+    with CCSD(eps, B, o, ladder_group_nvir=group) as cc:
         cc.set_amplitudes(t1, t2)
         cc.set_lambda(l1, l2)
         g1, g2 = cc.lambda_residual()

@@ -21,16 +21,19 @@ RESIDUAL_CASES = [(3, 4, 9), (5, 7, 13), (10, 40, 120), (12, 70, 150), (16, 67, 
                   (1, 9, 20), (2, 12, 30), (4, 1, 6), (1, 1, 3)]
 
 
+@pytest.mark.parametrize("group", [64, 0])
 @pytest.mark.parametrize("o,v,X", RESIDUAL_CASES)
-def test_residual_matches_oracle(lib, o, v, X):
+def test_residual_matches_oracle(lib, o, v, X, group):
+    """group: nvir up to which the particle ladder builds all rows' tiles in one product
+    (64, the default) or 0 (the per-row Hermitian build at every size)."""
     from paper_2103_08473_amd.exacc import CCSD
-    say("residual case", o, v, X)
+    say("residual case", o, v, X, "ladder_group_nvir", group)
     eps, B = make_system(o, v, X, seed=o * 1000 + v, sigma=0.2)
     t1, t2 = make_amplitudes(o, v, seed=7 + o, scale=0.1)
     ints = build_integrals(B, o)
     S1, S2 = residual(eps, ints, t1, t2)
     E = energy(eps, ints, t1, t2)
-    with CCSD(eps, B, o) as cc:
+    with CCSD(eps, B, o, ladder_group_nvir=group) as cc:
         cc.set_amplitudes(t1, t2)
         g1, g2 = cc.residual()
         ge = cc.energy()
@@ -320,8 +323,9 @@ def test_full_size_residual_samples(lib):
 
 
 # ---------------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("group", [64, 0])
 @pytest.mark.parametrize("o,v,X", [(10, 40, 120), (12, 70, 150), (1, 9, 20)])
-def test_fp32_phase_residual(lib, o, v, X):
+def test_fp32_phase_residual(lib, o, v, X, group):
     """FP32 contractions, FP64 assembly: the residual agrees with the FP64 oracle to FP32
     accuracy (sums of <= P_v products of unit roundoff 6e-8: 1e-5 of the largest |S|)."""
     from paper_2103_08473_amd import exacc
@@ -329,7 +333,7 @@ def test_fp32_phase_residual(lib, o, v, X):
     eps, B = make_system(o, v, X, seed=o * 1000 + v, sigma=0.2)
     t1, t2 = make_amplitudes(o, v, seed=7 + o, scale=0.1)
     S1, S2 = residual(eps, build_integrals(B, o), t1, t2)
-    with exacc.CCSD(eps, B, o, precision=exacc.MIXED_FP32) as cc:
+    with exacc.CCSD(eps, B, o, precision=exacc.MIXED_FP32, ladder_group_nvir=group) as cc:
         assert cc.phase() == (True, 0)
         cc.set_amplitudes(t1, t2)
         g1, g2 = cc.residual()
@@ -365,8 +369,9 @@ def test_mixed_precision_solve_matches_fp64_oracle(lib, o, v, X, seed):
     assert dT <= 1e-7
 
 
+@pytest.mark.parametrize("group", [64, 0])
 @pytest.mark.parametrize("o,v,X", [(10, 40, 120), (12, 70, 150), (16, 67, 131), (6, 110, 100)])
-def test_bf16x3_phase_residual(lib, o, v, X):
+def test_bf16x3_phase_residual(lib, o, v, X, group):
     """BF16x3 ladder (and FP32 elsewhere), FP64 assembly: agreement with the FP64 oracle at
     the split-BF16 level (each product ~2^-16 relative, FP32 sums: 1e-4 of the largest |S|).
     (6, 110, 100): the ladder contraction has K = P_v = 5995 (odd) over 47 output tiles, so it
@@ -376,7 +381,7 @@ def test_bf16x3_phase_residual(lib, o, v, X):
     eps, B = make_system(o, v, X, seed=o * 1000 + v, sigma=0.2)
     t1, t2 = make_amplitudes(o, v, seed=7 + o, scale=0.1)
     S1, S2 = residual(eps, build_integrals(B, o), t1, t2)
-    with exacc.CCSD(eps, B, o, precision=exacc.MIXED_BF16X3) as cc:
+    with exacc.CCSD(eps, B, o, precision=exacc.MIXED_BF16X3, ladder_group_nvir=group) as cc:
         cc.set_amplitudes(t1, t2)
         g1, g2 = cc.residual()
     scale = max(np.abs(S2).max(), np.abs(S1).max())

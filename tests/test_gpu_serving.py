@@ -25,7 +25,7 @@ def test_serving_overlap_and_alone_equals_mix(lib):
     warm = Request(99, 3, 21, 63, 15)   # code objects loaded before anything is timed
     warm.inputs = _make_inputs((3, 21, 63, 15))
     solve_one(warm, opts)
-    srv = run_stream(reqs, rate=50.0, hbm_budget=budget, max_active=4, opts=opts, producers=2)
+    srv = run_stream(reqs, rate=1000.0, hbm_budget=budget, max_active=4, opts=opts, producers=2)
     first = min(r.arrival for r in srv.done)
     makespan = max(r.finished for r in srv.done) - first
     rep = report(srv.done, makespan)
@@ -35,8 +35,9 @@ def test_serving_overlap_and_alone_equals_mix(lib):
     # requests overlapped: some request was admitted before another finished
     done = sorted(srv.done, key=lambda r: r.admitted)
     assert any(b.admitted < a.finished for a, b in zip(done, done[1:]))
-    # and memory admission made some wait
-    assert any(r.admitted - r.arrival > 0.05 for r in srv.done)
+    # and memory admission made some wait: a request at the head of the queue found a slot
+    # free but not enough of the HBM budget
+    assert any(r.mem_wait and r.admitted > r.arrival for r in srv.done)
     alone_wall = 0.0
     for r in sorted(srv.done, key=lambda r: r.k):
         eps, B = _make_inputs((r.nocc, r.nvir, r.naux, r.seed))
