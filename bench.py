@@ -217,14 +217,31 @@ def oracle_iteration(eps, B, o, ladder_rows_sample=6):
     step.  The ladder term, which does not fit in one run at this size, is timed on
     `ladder_rows_sample` of its rows a (each row builds <ab||cd> for all b, c, d and
     contracts it with tau: the same work for every a) and scaled to all v rows."""
+    import types
+
     import numpy as np
     import oracle.ccsd as occ
+    import oracle.integrals as oint
     hi = host_info()
     v = eps.size - o
     out = {"host": hi, "workload": "nocc=%d nvir=%d naux=%d" % (o, v, B.shape[0])}
 
     def say(msg):
         print("oracle iteration: " + msg, file=sys.stderr, flush=True)
+
+    # the oracle's own einsum calls report each one that takes over 2 s as it ends (one
+    # call of the residual takes minutes at this size)
+    def einsum(spec, *ops, **kw):
+        t = time.perf_counter()
+        r = np.einsum(spec, *ops, **kw)
+        dt = time.perf_counter() - t
+        if dt > 2.0:
+            say("einsum %s %.1f s" % (spec, dt))
+        return r
+    shim = types.SimpleNamespace(**{k: getattr(np, k) for k in dir(np) if not k.startswith("__")})
+    shim.einsum = einsum
+    saved = (occ.np, oint.np)
+    occ.np, oint.np = shim, shim
 
     t0 = time.perf_counter()
     ints = occ.build_integrals(B, o)
@@ -252,12 +269,14 @@ def oracle_iteration(eps, B, o, ladder_rows_sample=6):
     t0 = time.perf_counter()
     for a in rows:
         occ.ladder_rows(ints["B"], o, tau, int(a), int(a) + 1)
+        say("ladder row %d done" % a)
     per_row = (time.perf_counter() - t0) / len(rows)
     out["ladder_rows_timed"] = [int(a) for a in rows]
     out["ladder_s_per_row"] = round(per_row, 3)
     out["ladder_s"] = round(per_row * v, 1)
     say("ladder %.2f s per row, %.0f s for %d rows" % (per_row, per_row * v, v))
     out["iteration_s"] = round(out["residual_without_ladder_s"] + out["ladder_s"], 1)
+    occ.np, oint.np = saved
     return out
 
 

@@ -392,12 +392,12 @@ static void launch_cfg(const Gett<R>& g, hipStream_t s) {
     h.kslice = g.K > 0 ? g.K : 1;
     const int64_t wgs = (int64_t)tiles * nb;
     // long K: slices of >= 256 k up to ~1024 workgroups; outputs of a few tiles (small
-    // problems, whose time is the serial k-loop of each workgroup): slices of >= 64 k up to
+    // problems, whose time is the serial k-loop of each workgroup): slices of >= 32 k up to
     // ~256 workgroups
-    const bool long_k = wgs < 1024 && g.K >= 1024, few_tiles = wgs < 128 && g.K >= 128;
+    const bool long_k = wgs < 1024 && g.K >= 1024, few_tiles = wgs < 128 && g.K >= 64;
     if (g_ws && (long_k || few_tiles)) {
       int64_t want = long_k ? (1024 + wgs - 1) / wgs : (256 + wgs - 1) / wgs;
-      const int64_t kmin = long_k ? 256 : 64;
+      const int64_t kmin = long_k ? 256 : 32;
       want = want < (g.K + kmin - 1) / kmin ? want : (g.K + kmin - 1) / kmin;
       const int64_t per = (int64_t)g.M * g.N * nb * 2 * (int64_t)sizeof(R);
       const int64_t cap = per > 0 ? (int64_t)(g_ws_bytes / per) : 0;
