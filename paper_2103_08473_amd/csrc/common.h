@@ -125,8 +125,6 @@ void k_copy_bytes(void* d, const void* src, int64_t nbytes, hipStream_t s);
 // Acat[y][a][t][m] = conj(<x_t y_t||m a>), (x_0, y_0) = (k, i0 + y), (x_1, y_1) = (i0 + y, j)
 void k_triples_acat(const double* Vooov, int i0, int ni, int j, int k, int o, int v, double* out,
                     hipStream_t s);
-// Vjk[a][m] = conj(<j k||m a>)
-void k_triples_vjk(const double* Vooov, int j, int k, int o, int v, double* out, hipStream_t s);
 void k_triples_energy(const double* We, const double* Wm, const double* Voovv, const double* T2,
                       const double* t1, const double* eps, int i0, int ni, int j, int k, int o, int v,
                       double* partial, int nblk, double* out, hipStream_t s);

@@ -1015,25 +1015,6 @@ void k_copy_bytes(void* d, const void* src, int64_t nbytes, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
-// Vjk[a][m] = conj(<j k||m a>) (Vooov [x][y][m][a]): the excitation element of the sum over m
-// that is the same for every i of a triples batch, K (= m) contiguous
-__global__ void triples_vjk_kernel(const double* __restrict__ Vooov, int j, int k, int o, int v,
-                                   double* __restrict__ out) {
-  const int64_t tot = (int64_t)v * o;
-  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < tot; t += (int64_t)gridDim.x * TB) {
-    const int m = (int)(t % o), a = (int)(t / o);
-    const z g = ld(Vooov, (((int64_t)j * o + k) * o + m) * v + a);
-    st(out, t, z{g.x, -g.y});
-  }
-}
-
-void k_triples_vjk(const double* Vooov, int j, int k, int o, int v, double* out, hipStream_t s) {
-  const int64_t tot = (int64_t)v * o;
-  if (tot <= 0) return;
-  hipLaunchKernelGGL(triples_vjk_kernel, dim3(nblocks(tot)), dim3(TB), 0, s, Vooov, j, k, o, v, out);
-  HIPCHECK(hipGetLastError());
-}
-
 void k_triples_acat(const double* Vooov, int i0, int ni, int j, int k, int o, int v, double* out,
                     hipStream_t s) {
   const int64_t tot = (int64_t)ni * v * 2 * o;

@@ -1343,27 +1343,25 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out, double* ey_o
       1, std::min<int64_t>(std::min(red, o - 2), (int64_t)((free_b - small - tiles) / 2 / wrow)));
   h.use();
   check_budget(h, tiles + (size_t)cap * wrow + (size_t)(4 * cap * nblk + 4 * ooo) * 8 +
-                     (size_t)(cap * 2 + 1) * v * o * 16,
+                     (size_t)cap * v * 2 * o * 16,
                "triples temporaries");
-  double *Ve = nullptr, *We = nullptr, *Wm = nullptr, *part = nullptr, *tri = nullptr, *Acat = nullptr,
-         *Vjk = nullptr;
+  double *Ve = nullptr, *We = nullptr, *Wm = nullptr, *part = nullptr, *tri = nullptr, *Acat = nullptr;
   struct Free {  // released on every exit, a failed allocation included
     Handle& h;
-    double** p[7];
+    double** p[6];
     ~Free() {
       for (auto q : p) try {
           h.dfree(*q);
         } catch (...) {
         }
     }
-  } fr{h, {&Ve, &We, &Wm, &part, &tri, &Acat, &Vjk}};
+  } fr{h, {&Ve, &We, &Wm, &part, &tri, &Acat}};
   Ve = h.dalloc((int64_t)slots * red * pvv);
   We = h.dalloc(cap * pvv);
   Wm = h.dalloc(cap * pvv);
   part = h.dalloc(2 * cap * nblk);  // 4 doubles per block
   tri = h.dalloc(2 * ooo);          // (e4, e5, ey, -) at [i][j][k]
   Acat = h.dalloc(cap * v * 2 * o);
-  Vjk = h.dalloc((int64_t)v * o);
   // full t2 [i][j][a][b] into H4 and t2 packed over the virtual pair [k][m][(b<c)] into
   // TAU (FP64 work arrays rebuilt every iteration)
   k_unpack_full(h.x, h.x + 2 * (int64_t)o * v, nullptr, h.H4, o, v, s);
@@ -1450,9 +1448,9 @@ static void triples_impl(Handle& h, double* e4_out, double* e5_out, double* ey_o
               contract(s, "iatm,tmy->iay", MONE, view(Acat, {ni, v, 2, o}),
                        sview(T2pv + 2 * (int64_t)j * opv, {2, o, Pv}, {(int64_t)(k - j) * opv, Pv, 1}),
                        false, Wmv);
-              // sum_m <am||jk> t_im^bc, the excitation element gathered K-contiguous
-              k_triples_vjk(h.Vooov, j, k, o, v, Vjk, s);
-              contract(s, "am,imy->iay", MONE, view(Vjk, {v, o}),
+              // sum_m <am||jk> t_im^bc
+              contract(s, "ma,imy->iay", MONE,
+                       conj(sview(h.Vooov + 2 * ((int64_t)j * o + k) * ov, {o, v}, {(int64_t)v, 1})),
                        sview(T2pv + 2 * (int64_t)i0 * opv, {ni, o, Pv}, {opv, Pv, 1}), true, Wmv);
               k_triples_energy(We, Wm, h.Voovv, T2, h.x, h.eps, i0, ni, j, k, o, v, part, nblk, tri, s);
             }

@@ -455,8 +455,6 @@ int main() {
         sview(T2pv.p + 2 * (int64_t)j1 * opv, {2, o, Pv}, {(int64_t)(k1 - j1) * opv, Pv, 1}), false, Wm);
     run("iatm,tmy->iay", MONE, mk({ni, v, 2, o}),
         sview(T2pv.p + 2 * (int64_t)1 * opv, {2, o, Pv}, {opv, Pv, 1}), true, Wm);
-    // the i-independent element gathered as [a][m] (K contiguous)
-    run("am,imy->iay", MONE, mk({v, o}), sview(T2pv.p, {ni, o, Pv}, {opv, Pv, 1}), true, Wm);
   }
   // DF factors: transform and metric GEMMs, the Newton-Schulz product
   {
