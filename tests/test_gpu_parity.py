@@ -345,8 +345,9 @@ def test_fp32_phase_residual(lib, o, v, X, group):
     assert e1 + e2 > 1e-12          # the FP32 phase really ran in FP32
 
 
+@pytest.mark.parametrize("group", [64, 0])
 @pytest.mark.parametrize("o,v,X,seed", [(6, 40, 120, 2), (8, 48, 144, 3)])
-def test_mixed_precision_solve_matches_fp64_oracle(lib, o, v, X, seed):
+def test_mixed_precision_solve_matches_fp64_oracle(lib, o, v, X, seed, group):
     """FP32 phase, switch below 1e-5, >= 3 FP64 iterations to 1e-10: |dE| <= 1e-7 Eh
     against the converged FP64 oracle (and the amplitudes to 1e-7)."""
     from paper_2103_08473_amd import exacc
@@ -355,7 +356,8 @@ def test_mixed_precision_solve_matches_fp64_oracle(lib, o, v, X, seed):
     ref = oracle.solve(eps, B, o, max_iter=80, tol=1e-10)
     assert ref.converged
     phases = []
-    with exacc.CCSD(eps, B, o, precision=exacc.MIXED_FP32, tol=1e-10, max_iter=80) as cc:
+    with exacc.CCSD(eps, B, o, precision=exacc.MIXED_FP32, tol=1e-10, max_iter=80,
+                    ladder_group_nvir=group) as cc:
         e, conv, hist = cc.solve(callback=lambda it, E, r: phases.append(cc.phase()[0]))
         t1, t2 = cc.amplitudes()
         _, n64 = cc.phase()
@@ -391,12 +393,16 @@ def test_bf16x3_phase_residual(lib, o, v, X, group):
     assert e1 <= 1e-4 and e2 <= 1e-4
 
 
-def test_bf16x3_solve_matches_fp64_oracle(lib):
+@pytest.mark.parametrize("group", [64, 0])
+def test_bf16x3_solve_matches_fp64_oracle(lib, group):
+    """Low-precision, defect-corrected and final FP64 phases; the ladder grouped over all
+    rows (64) and per row (0)."""
     from paper_2103_08473_amd import exacc
     o, v, X, seed = 6, 40, 120, 2
     eps, B = make_system(o, v, X, seed=seed)
     ref = oracle.solve(eps, B, o, max_iter=80, tol=1e-10)
-    with exacc.CCSD(eps, B, o, precision=exacc.MIXED_BF16X3, tol=1e-10, max_iter=80) as cc:
+    with exacc.CCSD(eps, B, o, precision=exacc.MIXED_BF16X3, tol=1e-10, max_iter=80,
+                    ladder_group_nvir=group) as cc:
         e, conv, hist = cc.solve()
         t1, t2 = cc.amplitudes()
     dE = abs(e - ref.energy)
