@@ -346,10 +346,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="FP64 leg only")
     ap.add_argument("--no-solve", action="store_true",
                     help="FP64 timed steps only (no solve to convergence, no other leg): for profiler runs")
-    ap.add_argument("--serving-requests", type=int, default=16)
-    ap.add_argument("--serving-rate", type=float, default=0.157,
-                    help="Poisson arrivals per second (0.8 x the 0.196 solves/s the serving stream "
-                         "sustained when saturated)")
+    ap.add_argument("--serving-requests", type=int, default=32)
+    ap.add_argument("--serving-rate", type=float, default=0.29,
+                    help="Poisson arrivals per second (0.8 x the 0.36 solves/s requests 0-127 of the "
+                         "serving stream completed while the server was saturated)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="first run one plain device-to-device copy of this many GiB (a known-size "
                          "kernel to scale hardware byte counters by)")
