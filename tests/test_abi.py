@@ -57,6 +57,20 @@ def test_df_factors_rejects_bad_sizes_before_touching_the_device():
 def test_new_options_default_to_automatic():
     o = exacc.default_opts()
     assert o.triples_occ_block == 0 and o.doubles_only == 0 and o.cc2 == 0
+    assert o.ladder_defect_correction == 1 and o.graph_residual == 0 and o.ladder_group_nvir == 64
+
+
+def test_grouped_ladder_scratch_is_planned():
+    """With all ladder rows in one product (nvir <= ladder_group_nvir) the tile scratch holds
+    v^4 complex elements instead of one row's v (v - 1) v; nothing else in the plan changes."""
+    v = 40
+    grouped = exacc.memory_estimate(6, v, 120)
+    per_row = exacc.memory_estimate(6, v, 120, ladder_group_nvir=0)
+    assert grouped - per_row == (v ** 4 - v * (v - 1) * v) * 16
+    # above the threshold, or with a ladder chunk smaller than the pair range, per row
+    assert exacc.memory_estimate(6, 65, 120) == exacc.memory_estimate(6, 65, 120, ladder_group_nvir=0)
+    assert exacc.memory_estimate(6, v, 120, ladder_chunk_pairs=100) == \
+        exacc.memory_estimate(6, v, 120, ladder_chunk_pairs=100, ladder_group_nvir=0)
 
 
 def test_bench_runs_on_one_gpu_only():
