@@ -793,10 +793,13 @@ void k_dress_vo(T* Vt, const T* Bt, const T* Q, int o, int v, int n, int X, hipS
 //        + t_ki^ab t_j^c
 //   e4 += -6 |W~|^2 / D,  e5 += -6 Re(conj(Z~) W~) / D,  ey += 6 Re(conj(Y~) W~),
 //   D = e_a + e_b + e_c - e_i - e_j - e_k.
-// One workgroup per triple of 8-wide virtual tiles (tA <= tB <= tC): the six 8x8x8 cubes of
-// packed values that W~ needs on (A, B, C) are staged in LDS, each read with its
-// contiguous index fastest (every global read coalesced), then each thread evaluates its
-// a < b < c points.  Block partial sums (e4, e5, ey) to part[4 * (y * gridDim.x + block)].
+// One workgroup per triple of 8-wide virtual tiles (tA <= tB <= tC).  Staged in LDS, each
+// read with its contiguous index fastest (every global read coalesced): the six 8x8x8 cubes
+// of packed values that W~ needs on (A, B, C); the 8x8 blocks of <xy||pq> and t_xy^pq for
+// the three occupied pairs (ij, jk, ki) and the three virtual tile pairs (AB, CA, BC) that
+// Z~ and Y~ read; and t_x^p for x in (i, j, k) on the three tiles.  Then each thread
+// evaluates its a < b < c points.  Block partial sums (e4, e5, ey) to
+// part[4 * (y * gridDim.x + block)].
 __global__ void triples_energy_kernel(const double* __restrict__ Web, const double* __restrict__ Wmb,
                                       const double* __restrict__ Voovv,
                                       const double* __restrict__ T2, const double* __restrict__ t1,
@@ -809,29 +812,6 @@ __global__ void triples_energy_kernel(const double* __restrict__ Web, const doub
   // packed parts at p < q (p, q, r < v)
   auto Ep = [&](int p, int q, int r) { return ld(We, pidx(p, q, v) * v + r); };
   auto Mp = [&](int r, int p, int q) { return ld(Wm, (int64_t)r * Pv + pidx(p, q, v)); };
-  auto Vc = [&](int x, int y, int a, int b) {  // <ab||xy> = conj(<xy||ab>)
-    const z g = ld(Voovv, ((int64_t)x * o + y) * vv + (int64_t)a * v + b);
-    return z{g.x, -g.y};
-  };
-  auto T1 = [&](int x, int a) { return ld(t1, (int64_t)x * v + a); };
-  auto Tt = [&](int x, int y, int a, int b) { return ld(T2, ((int64_t)x * o + y) * vv + (int64_t)a * v + b); };
-  auto Zf = [&](int a, int b, int c) {
-    z r = mul(Vc(i, j, a, b), T1(k, c));
-    r = add(r, mul(Vc(j, k, a, b), T1(i, c)));
-    return add(r, mul(Vc(k, i, a, b), T1(j, c)));
-  };
-  auto Yf = [&](int a, int b, int c) {
-    z d = mul(mul(T1(i, a), T1(j, b)), T1(k, c));
-    d = sub(d, mul(mul(T1(j, a), T1(i, b)), T1(k, c)));
-    d = add(d, mul(mul(T1(j, a), T1(k, b)), T1(i, c)));
-    d = sub(d, mul(mul(T1(k, a), T1(j, b)), T1(i, c)));
-    d = add(d, mul(mul(T1(k, a), T1(i, b)), T1(j, c)));
-    d = sub(d, mul(mul(T1(i, a), T1(k, b)), T1(j, c)));
-    z r = scal(1.0 / 3.0, d);
-    r = add(r, mul(Tt(i, j, a, b), T1(k, c)));
-    r = add(r, mul(Tt(j, k, a, b), T1(i, c)));
-    return add(r, mul(Tt(k, i, a, b), T1(j, c)));
-  };
   // tile triple of this workgroup
   const int nt = (v + 7) / 8;
   int rem = (int)blockIdx.x, ta = 0;
@@ -846,11 +826,9 @@ __global__ void triples_energy_kernel(const double* __restrict__ Web, const doub
   }
   const int tc = tb + rem;
   const int a0 = 8 * ta, b0 = 8 * tb, c0 = 8 * tc;
-  // cube q at LDS index x * 73 + y * 9 + w holds its value for (a, b, c) = (a0+x, b0+y, c0+w)
-  // (pitches 73 and 9: the transposed stores of cubes 1, 2 and 5 fall in distinct banks);
+  // cube q at LDS index (x * 8 + y) * 8 + w holds its value for (a, b, c) = (a0+x, b0+y, c0+w);
   // entries whose pair is not p < q (unused by a < b < c) are zero
-  constexpr int CQ = 8 * 73;
-  __shared__ double qr[6][CQ], qi[6][CQ];
+  __shared__ double qr[6][512], qi[6][512];
   for (int e = threadIdx.x; e < 512; e += TB) {
     const int u = e >> 6, m = (e >> 3) & 7, f = e & 7;  // f fastest
     z g[6];
@@ -862,13 +840,13 @@ __global__ void triples_energy_kernel(const double* __restrict__ Web, const doub
       g[0] = (in && a < b) ? Ep(a, b, c) : z{0, 0};
       g[3] = (in && b < c) ? Mp(a, b, c) : z{0, 0};
       g[4] = (in && a < c) ? Mp(b, a, c) : z{0, 0};
-      at[0] = at[3] = at[4] = u * 73 + m * 9 + f;
+      at[0] = at[3] = at[4] = (u * 8 + m) * 8 + f;
     }
     // 1: We(bc, a), a fastest
     {
       const int b = b0 + u, c = c0 + m, a = a0 + f;
       g[1] = (a < v && b < v && c < v && b < c) ? Ep(b, c, a) : z{0, 0};
-      at[1] = f * 73 + u * 9 + m;
+      at[1] = (f * 8 + u) * 8 + m;
     }
     // 2: We(ac, b), b fastest;  5: Wm(c, ab), b fastest
     {
@@ -876,7 +854,7 @@ __global__ void triples_energy_kernel(const double* __restrict__ Web, const doub
       const bool in = a < v && b < v && c < v;
       g[2] = (in && a < c) ? Ep(a, c, b) : z{0, 0};
       g[5] = (in && a < b) ? Mp(c, a, b) : z{0, 0};
-      at[2] = at[5] = u * 73 + f * 9 + m;
+      at[2] = at[5] = (u * 8 + f) * 8 + m;
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -884,18 +862,70 @@ __global__ void triples_energy_kernel(const double* __restrict__ Web, const doub
       qi[q][at[q]] = g[q].y;
     }
   }
+  // block 3 p + r, cell 8 row + col: <pair p||tile pair r> (conjugated) and t_(pair p)^(tile pair
+  // r); pairs p = (ij, jk, ki), tile pairs r = (AB, CA, BC) as (row, col); t1s[x][8 tile + w]
+  // = t_x^(tile start + w) for x = (i, j, k), tiles (A, B, C)
+  __shared__ double vr[9][64], vi[9][64], sr[9][64], si[9][64], t1r[3][24], t1i[3][24];
+  const int xs[3] = {i, j, k};
+  for (int e = threadIdx.x; e < 9 * 64; e += TB) {
+    const int blk = e >> 6, cell = e & 63, r = cell >> 3, c = cell & 7;
+    const int p = blk / 3, role = blk - 3 * p;
+    const int x = xs[p], y = xs[p == 2 ? 0 : p + 1];
+    const int row = (role == 0 ? a0 : role == 1 ? c0 : b0) + r;
+    const int col = (role == 0 ? b0 : role == 1 ? a0 : c0) + c;
+    z g{0, 0}, h{0, 0};
+    if (row < v && col < v) {
+      const int64_t off = ((int64_t)x * o + y) * vv + (int64_t)row * v + col;
+      g = ld(Voovv, off);
+      h = ld(T2, off);
+    }
+    vr[blk][cell] = g.x;
+    vi[blk][cell] = -g.y;
+    sr[blk][cell] = h.x;
+    si[blk][cell] = h.y;
+  }
+  for (int e = threadIdx.x; e < 72; e += TB) {
+    const int xi = e / 24, q = e - 24 * xi, tile = q >> 3, w = q & 7;
+    const int col = (tile == 0 ? a0 : tile == 1 ? b0 : c0) + w;
+    const z g = col < v ? ld(t1, (int64_t)xs[xi] * v + col) : z{0, 0};
+    t1r[xi][q] = g.x;
+    t1i[xi][q] = g.y;
+  }
   __syncthreads();
+  auto T1 = [&](int x, int q) { return z{t1r[x][q], t1i[x][q]}; };
+  auto Vs = [&](int blk, int cell) { return z{vr[blk][cell], vi[blk][cell]}; };
+  auto Ts = [&](int blk, int cell) { return z{sr[blk][cell], si[blk][cell]}; };
+  // Z(p, q, r) and Y(p, q, r) for (p, q, r) one of (a, b, c), (c, a, b), (b, c, a): tile pair
+  // `role` of (p, q), its cell, and the t1s columns qp, qq, qr of p, q, r
+  auto Zr = [&](int role, int cell, int qr_) {
+    z r = mul(Vs(role, cell), T1(2, qr_));
+    r = add(r, mul(Vs(3 + role, cell), T1(0, qr_)));
+    return add(r, mul(Vs(6 + role, cell), T1(1, qr_)));
+  };
+  auto Yr = [&](int role, int cell, int qp, int qq, int qr_) {
+    z d = mul(mul(T1(0, qp), T1(1, qq)), T1(2, qr_));
+    d = sub(d, mul(mul(T1(1, qp), T1(0, qq)), T1(2, qr_)));
+    d = add(d, mul(mul(T1(1, qp), T1(2, qq)), T1(0, qr_)));
+    d = sub(d, mul(mul(T1(2, qp), T1(1, qq)), T1(0, qr_)));
+    d = add(d, mul(mul(T1(2, qp), T1(0, qq)), T1(1, qr_)));
+    d = sub(d, mul(mul(T1(0, qp), T1(2, qq)), T1(1, qr_)));
+    z r = scal(1.0 / 3.0, d);
+    r = add(r, mul(Ts(role, cell), T1(2, qr_)));
+    r = add(r, mul(Ts(3 + role, cell), T1(0, qr_)));
+    return add(r, mul(Ts(6 + role, cell), T1(1, qr_)));
+  };
   double e4 = 0, e5 = 0, ey = 0;
   const double eo = eps[i] + eps[j] + eps[k];
   for (int e = threadIdx.x; e < 512; e += TB) {
     const int x = e >> 6, y = (e >> 3) & 7, w = e & 7;
     const int a = a0 + x, b = b0 + y, c = c0 + w;
     if (!(c < v && a < b && b < c)) continue;
-    const int q = x * 73 + y * 9 + w;
-    const z wt{qr[0][q] + qr[1][q] - qr[2][q] + qr[3][q] - qr[4][q] + qr[5][q],
-               qi[0][q] + qi[1][q] - qi[2][q] + qi[3][q] - qi[4][q] + qi[5][q]};
-    const z zz = add(Zf(a, b, c), add(Zf(c, a, b), Zf(b, c, a)));
-    const z yy = add(Yf(a, b, c), add(Yf(c, a, b), Yf(b, c, a)));
+    const z wt{qr[0][e] + qr[1][e] - qr[2][e] + qr[3][e] - qr[4][e] + qr[5][e],
+               qi[0][e] + qi[1][e] - qi[2][e] + qi[3][e] - qi[4][e] + qi[5][e]};
+    const int qa = x, qb = 8 + y, qc = 16 + w;
+    const z zz = add(Zr(0, x * 8 + y, qc), add(Zr(1, w * 8 + x, qb), Zr(2, y * 8 + w, qa)));
+    const z yy = add(Yr(0, x * 8 + y, qa, qb, qc),
+                     add(Yr(1, w * 8 + x, qc, qa, qb), Yr(2, y * 8 + w, qb, qc, qa)));
     const double D = eps[o + a] + eps[o + b] + eps[o + c] - eo;
     e4 -= 6.0 * (wt.x * wt.x + wt.y * wt.y) / D;
     e5 -= 6.0 * (zz.x * wt.x + zz.y * wt.y) / D;
