@@ -887,17 +887,25 @@ static void launch_bf16x3(const Gett<float>& g, hipStream_t s) {
     h.C = g.C + 2 * b0 * g.c_b;
     h.kslice = g.K > 0 ? g.K : 1;
     h.ws = nullptr;
-    // split K when the output gives fewer workgroups than CUs (one 16-wave
-    // workgroup per CU): slices of >= 1024 k, a multiple of BK (keeps the
-    // 16-byte alignment of the k-pair loads), fixed-order reduction
+    // split K when the output gives too few workgroups for whole rounds over the CUs (one
+    // 16-wave workgroup per CU): with nz slices the launch takes ceil(wgs nz / 256) rounds
+    // of K / nz each, so nz is the smallest count within 2% of the best rounds / nz, taken
+    // when it saves at least 10%; slices of >= 1024 k, a multiple of BK (keeps the 16-byte
+    // alignment of the k-pair loads), fixed-order reduction
     int nz = 1;
     const int64_t wgs = (int64_t)tiles * nb;
-    if (g_ws && wgs < 256 && g.K >= 2048) {
-      int64_t want = (256 + wgs - 1) / wgs;
-      want = want < g.K / 1024 ? want : g.K / 1024;
+    if (g_ws && wgs < 1024 && g.K >= 2048) {
       const int64_t per = (int64_t)g.M * g.N * nb * 2 * (int64_t)sizeof(float);
       const int64_t cap = per > 0 ? (int64_t)(g_ws_bytes / per) : 0;
-      if (want > cap) want = cap;
+      int64_t zmax = g.K / 1024;
+      if (zmax > cap) zmax = cap;
+      if (zmax > 32) zmax = 32;
+      auto cost = [&](int64_t z) { return (double)((wgs * z + 255) / 256) / (double)z; };
+      double best = cost(1);
+      for (int64_t z = 2; z <= zmax; ++z) best = cost(z) < best ? cost(z) : best;
+      int64_t want = 1;
+      while (want < zmax && cost(want) > 1.02 * best) ++want;
+      if (cost(want) > 0.9 * cost(1)) want = 1;  // under 10% to gain: no split
       if (want >= 2) {
         int64_t ks = (g.K + want - 1) / want;
         ks = (ks + BK - 1) / BK * BK;
