@@ -396,13 +396,25 @@ static void launch_cfg(const Gett<R>& g, hipStream_t s) {
     // ~256 workgroups
     const bool long_k = wgs < 1024 && g.K >= 1024, few_tiles = wgs < 128 && g.K >= 64;
     if (g_ws && (long_k || few_tiles)) {
-      int64_t want = long_k ? (1024 + wgs - 1) / wgs : (256 + wgs - 1) / wgs;
       const int64_t kmin = long_k ? 256 : 32;
-      want = want < (g.K + kmin - 1) / kmin ? want : (g.K + kmin - 1) / kmin;
       const int64_t per = (int64_t)g.M * g.N * nb * 2 * (int64_t)sizeof(R);
       const int64_t cap = per > 0 ? (int64_t)(g_ws_bytes / per) : 0;
-      if (want > cap) want = cap;
-      if (want > 1024) want = 1024;
+      int64_t zmax = (g.K + kmin - 1) / kmin;
+      if (zmax > cap) zmax = cap;
+      if (zmax > 1024) zmax = 1024;
+      int64_t want = 1;
+      if (few_tiles && !long_k) {
+        want = (256 + wgs - 1) / wgs;
+      } else {
+        // whole rounds of workgroups (two per CU, 512 at a time): nz slices take
+        // ceil(wgs nz / 512) rounds of K / nz each; the smallest nz within 2% of the best
+        // rounds / nz
+        auto cost = [&](int64_t z) { return (double)((wgs * z + 511) / 512) / (double)z; };
+        double best = cost(1);
+        for (int64_t z = 2; z <= zmax; ++z) best = cost(z) < best ? cost(z) : best;
+        while (want < zmax && cost(want) > 1.02 * best) ++want;
+      }
+      if (want > zmax) want = zmax;
       if (want >= 2) {
         int64_t ks = (g.K + want - 1) / want;
         ks = (ks + 31) / 32 * 32;  // a multiple of every BK
