@@ -409,3 +409,38 @@ def test_bf16x3_solve_matches_fp64_oracle(lib, group):
     dT = max(np.abs(t1 - ref.t1).max(), np.abs(t2 - ref.t2).max())
     say("  bf16x3 solve: iterations %d, |dE| %.2e Eh, max|dT| %.2e" % (len(hist), dE, dT))
     assert conv and dE <= 1e-7 and dT <= 1e-7
+
+
+@pytest.mark.parametrize("prec,variant", [("MIXED_BF16X3", "no_correction"), ("MIXED_BF16X3", "ladder_only"),
+                                          ("MIXED_FP32", "ladder_only")])
+def test_mixed_tail_variants_match_fp64_oracle(lib, prec, variant):
+    """The other tails of a mixed solve: without the corrected iterations (full FP64 from the
+    switch on), and with the corrected ladder and C term but the ring in FP64, which create
+    chooses when the ring part's reference arrays do not fit the HBM budget (as at
+    60/540/1800 in device memory).  Both reach the FP64 oracle's converged answer."""
+    from paper_2103_08473_amd import exacc
+    o, v, X, seed = 6, 40, 120, 2
+    p = getattr(exacc, prec)
+    eps, B = make_system(o, v, X, seed=seed)
+    ref = oracle.solve(eps, B, o, max_iter=80, tol=1e-10)
+    opts = dict(precision=p, tol=1e-10, max_iter=80)
+    if variant == "no_correction":
+        opts["ladder_defect_correction"] = 0
+    else:
+        full = exacc.memory_estimate(o, v, X, precision=p)
+        ladder_only = exacc.memory_estimate(o, v, X, precision=p, hbm_budget_bytes=full - 1)
+        assert ladder_only < full     # the ring part is what the smaller budget leaves out
+        opts["hbm_budget_bytes"] = ladder_only
+    phases = []
+    with exacc.CCSD(eps, B, o, **opts) as cc:
+        e, conv, hist = cc.solve(callback=lambda it, E, r: phases.append(cc.phase()[0]))
+        t1, t2 = cc.amplitudes()
+        _, n64 = cc.phase()
+    dE = abs(e - ref.energy)
+    dT = max(np.abs(t1 - ref.t1).max(), np.abs(t2 - ref.t2).max())
+    say("  %s %s: iterations %d (low %d, corrected %d, final FP64 %d), |dE| %.2e Eh, max|dT| %.2e"
+        % (prec, variant, len(hist), phases.count(1) + 1, phases.count(2), n64, dE, dT))
+    assert conv and n64 >= 3 and phases[0] == 1 and phases[-1] == 0
+    assert (2 in phases) == (variant == "ladder_only")
+    assert dE <= 1e-7 and dT <= 1e-7
+
