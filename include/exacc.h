@@ -41,7 +41,7 @@ enum {
   EXACC_ERR_NOMEM = -2,         /* memory plan exceeds hbm_budget_bytes or a device allocation failed */
   EXACC_ERR_DEVICE = -3,        /* a HIP runtime error (text via exacc_last_error) */
   EXACC_ERR_DIVERGED = -4,      /* energy or step norm non-finite or grew 1e6-fold; handle stays readable */
-  EXACC_ERR_UNSUPPORTED = -5    /* option value not implemented by this build */
+  EXACC_ERR_UNSUPPORTED = -5    /* option value not implemented by this library */
 };
 
 enum { EXACC_FP64 = 0, EXACC_MIXED_FP32 = 1, EXACC_MIXED_BF16X3 = 2 };
