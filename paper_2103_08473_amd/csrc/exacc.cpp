@@ -120,7 +120,8 @@ static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
   // product of C^{kb}_{ij} the kept FP32 vovv class and the FP64 reference product
   const size_t ring_dc = dc ? B16(p.L) + B16(p.oovv) + B16(p.oovv) + B16(p.oovv) / 2 +
                                   B16(oo * X + (int64_t)v * o * X + (int64_t)o * v) +
-                                  B16((int64_t)v * o * p.Pv) / 2 + B16(p.Po * v * o)
+                                  B16((int64_t)v * o * p.Pv) / 2 + B16(p.Po * v * o) +
+                                  (op.precision == EXACC_MIXED_BF16X3 ? B16(n * n * X) / 2 : 0)
                             : 0;
   const size_t phase64 = common + big64 + vovv_tmp + dc;
   const size_t phase32 = common + big32;
@@ -431,7 +432,8 @@ static void ensure_fp64_classes(Handle& h, bool keep_low_ladder = false) {
   if (h.Voovv && h.Vvovv_p) return;
   Scope sc(h, "switch_to_fp64");
   if (!keep_low_ladder || !h.Bvs) h.dfree(h.Bvs);
-  if (!keep_low_ladder || h.Bvs) h.dfree(h.Bt32);
+  // the FP32 factors stay for the corrected ring's t1 terms (and, in the FP32 mode, the ladder)
+  if (!keep_low_ladder || (h.Bvs && !h.P.ring_dc)) h.dfree(h.Bt32);
   h.dfree(h.Voooo32);
   h.dfree(h.Vooov32);
   if (!keep_low_ladder || !h.P.ring_dc) h.dfree(h.Voovv32);
@@ -641,8 +643,10 @@ static void ladder_apply_herm(Handle& h, const Work<R>& w, const R* F, int64_t r
 // exactly, where d = current - reference, H1 the t1-linear DF terms of H and Xp the
 // ring operand (t2 / 2 + t1 t1): the differences are formed in FP64 from the amplitudes,
 // the three o^3 v^3 products run in the low precision of the mode (their rounding is
-// relative to the small differences), the t1-linear DF part of dH in FP64.  Scratch: Z
-// and H4 as FP32 halves (dT2 then Tq; dTq, dXp), Xp for dH in FP64 before it takes R.
+// relative to the small differences), and so do the two o^2 v^2 naux products of H1(dt1),
+// on the FP32 factors kept through the corrected phase (its o^3 v^2 ooov term stays FP64).
+// Scratch: Z and H4 as FP32 halves (dT2 then Tq; dTq, dXp), Xp for the FP64 part of dH
+// before it takes R, the FP64 DF buffers Ud and Vtd for their FP32 counterparts.
 static void ring_defect_corrected(Handle& h, const Work<double>& w, const Views<double>& b, bool ccd) {
   const int o = h.P.o, v = h.P.v, X = h.P.X;
   const hipStream_t s = h.s;
@@ -659,7 +663,27 @@ static void ring_defect_corrected(Handle& h, const Work<double>& w, const Views<
     k_ring_operands<float>(Za, h.x, Ha, Hb, o, v, s, h.x_ref);  // dTq, dXp
     k_cast(w.Tq, Za, 2 * oovv, s);                               // Tq in FP32
   }
-  if (!ccd) {
+  if (!ccd && h.Bt32) {
+    // H1(dt1) on the FP32 factors: the two o^2 v^2 naux products in the mode's low
+    // precision (their rounding is relative to dt1), the o^3 v^2 ooov term in FP64
+    Scope sc(h, "ring_dc");
+    Views<float> b32 = bviews(h, h.Bt32);
+    float* Vtd32 = reinterpret_cast<float*>(h.Vtd);  // v o X complex, half of the FP64 buffer
+    float* t1d32 = Vtd32 + 2 * (int64_t)v * o * X;   // o v complex, in the other half
+    float* Ud32 = reinterpret_cast<float*>(h.Ud);
+    k_cast(h.t1d, t1d32, 2 * ov, s);
+    auto t1d = view(t1d32, {o, v});
+    auto Ud = view(Ud32, {o, o, X});
+    auto Vtd = view(Vtd32, {v, o, X});
+    contract(s, "kdP,id->kiP", ONE, b32.Bov, t1d, false, Ud);
+    contract(s, "acP,ic->aiP", ONE, b32.Bvv, t1d, false, Vtd);
+    contract(s, "klic,la->aikc", MONE, view(w.Vooov, {o, o, o, v}), view(h.t1d, {o, v}), false,
+             view(w.Xp, {v, o, o, v}));
+    k_cast(w.Xp, h.D32, 2 * oovv, s);
+    auto D = view(h.D32, {v, o, o, v});
+    contract(s, "acP,kiP->aikc", ONE, b32.Bvv, Ud, true, D, rk);
+    contract(s, "aiP,kcP->aikc", MONE, Vtd, b32.Bov, true, D, rk);
+  } else if (!ccd) {
     Scope sc(h, "ring_dc");
     auto t1d = view(h.t1d, {o, v});
     auto Ud = view(h.Ud, {o, o, X});
