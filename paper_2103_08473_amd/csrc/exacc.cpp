@@ -945,8 +945,18 @@ static void compute_residual(Handle& h) {
       contract(s, "klic,jc->klij", ONE, Vooov, t1, true, Af);
       contract(s, "kljc,ic->klij", MONE, Vooov, t1, true, Af);
     }
-    contract(s, "klcd,ijcd->klij", HALF, Voovv, TAU, true, Af);
-    if (Po > 0) k_pack_last2<R>(w.Ap, w.Af, h.rowmap_o, Po, o, (int64_t)o * o, s);
+    if constexpr (sizeof(R) == sizeof(double)) {
+      // 1/2 sum_cd <kl||cd> tau_ij^cd = sum_{c<d} <kl||cd> tau_ij^cd, formed on the packed
+      // pairs (k<l), (i<j), (c<d) that A enters the hole ladder with: P_o^2 P_v complex
+      // multiply-adds instead of o^4 v^2 / 2
+      if (Po > 0) {
+        k_pack_last2<R>(w.Ap, w.Af, h.rowmap_o, Po, o, (int64_t)o * o, s);
+        contract(s, "qx,px->qp", ONE, view(h.Voovv_p, {Po, Pv}), taup, true, view(w.Ap, {Po, Po}));
+      }
+    } else {
+      contract(s, "klcd,ijcd->klij", HALF, Voovv, TAU, true, Af);
+      if (Po > 0) k_pack_last2<R>(w.Ap, w.Af, h.rowmap_o, Po, o, (int64_t)o * o, s);
+    }
     contract(s, "qp,qx->px", ONE, view(w.Ap, {Po, Po}), taup, false, Znp);
   }
   // particle ladder: Znp[ij][ab] += sum_{c<d} tau[ij][cd] <ab||cd>, <ab||cd> = (ac|bd) - (ad|bc)
