@@ -105,7 +105,7 @@ static Plan make_plan(int o, int v, int X, const exacc_ccsd_opts& op) {
                         ? B16(p.vv * bf16x3_split_k(X) / 2)       // split B_vv rows, 8 B per k
                         : 0;
   const size_t big32 = (B16(p.oovv) + B16((int64_t)v * o * p.Pv) + B16(n * n * X) + B16(oo * oo) +
-                        B16(oo * o * v)) / 2 + bvs;               // FP32 copies
+                        B16(oo * o * v) + B16(p.Po * p.Pv)) / 2 + bvs;  // FP32 copies
   const size_t vovv_tmp = B16(p.vovv_chunk * vovv_row) + B16(p.vovv_chunk * o * p.Pv);
   const size_t create_peak = B16(n * n * X) * 2 + B16(p.oovv) + big32 + vovv_tmp;  // staging
   // defect-corrected ladder after the switch: tau_ref and Zref, and the low-precision
@@ -179,6 +179,7 @@ struct Handle {
   double *Hac, *Gac, *Hki, *Gki, *Hkc, *y, *U, *Vt, *M1, *Y, *S1, *Cp, *Cf, *Af, *Ap;
   double *Ta, *W, *t1w;
   // FP32 copies of B and the stored integral classes (mixed precision only)
+  float *Voovv_p32 = nullptr;  // FP32 <kl||cd> packed over k<l, c<d (low-precision hole ladder)
   float *Bt32 = nullptr, *Voooo32 = nullptr, *Vooov32 = nullptr, *Voovv32 = nullptr,
         *Vvovv_p32 = nullptr;
   // BF16x3 mode: the virtual-virtual factor rows B[(a,c)][P] split once into
@@ -436,6 +437,7 @@ static void ensure_fp64_classes(Handle& h, bool keep_low_ladder = false) {
   if (!keep_low_ladder || (h.Bvs && !h.P.ring_dc)) h.dfree(h.Bt32);
   h.dfree(h.Voooo32);
   h.dfree(h.Vooov32);
+  h.dfree(h.Voovv_p32);
   if (!keep_low_ladder || !h.P.ring_dc) h.dfree(h.Voovv32);
   if (!keep_low_ladder || !h.P.ring_dc) h.dfree(h.Vvovv_p32);
   h.Voovv = h.dalloc(h.P.oovv);
@@ -952,6 +954,11 @@ static void compute_residual(Handle& h) {
       if (Po > 0) {
         k_pack_last2<R>(w.Ap, w.Af, h.rowmap_o, Po, o, (int64_t)o * o, s);
         contract(s, "qx,px->qp", ONE, view(h.Voovv_p, {Po, Pv}), taup, true, view(w.Ap, {Po, Po}));
+      }
+    } else if (h.Voovv_p32) {  // the same on the FP32 copy of the packed class
+      if (Po > 0) {
+        k_pack_last2<R>(w.Ap, w.Af, h.rowmap_o, Po, o, (int64_t)o * o, s);
+        contract(s, "qx,px->qp", ONE, view(h.Voovv_p32, {Po, Pv}), taup, true, view(w.Ap, {Po, Po}));
       }
     } else {
       contract(s, "klcd,ijcd->klij", HALF, Voovv, TAU, true, Af);
@@ -1985,6 +1992,7 @@ static Handle* create_impl(int o, int v, int X, const double* eps, const double*
         }
         h->Voooo32 = mk32(h->Voooo, oo * oo);
         h->Vooov32 = mk32(h->Vooov, oo * o * v);
+        h->Voovv_p32 = mk32(h->Voovv_p, P.Po * P.Pv);
         {
           // [k][c][l][d] layout for the FP32 copy (contiguous (l, d) for the ring build)
           Views<double> b = bviews(*h, h->Bt);
