@@ -415,6 +415,10 @@ int main() {
       run("cP,bdP->cbd", ONE, Ba, Bb, false, mk({v, nb, v}));
     }
   }
+  // small nvir: the ladder tiles of all rows in one product ((a, c) rows at the factor's row
+  // stride), and the hole ladder's tau term on packed pairs
+  run("acP,bdP->acbd", ONE, Bvv, Bvv, false, mk({v, v, v, v}));
+  run("qx,px->qp", ONE, mk({Po, Pv}), mk({Po, Pv}), true, mk({Po, Po}));
   // perturbative triples: packed tiles of an occupied block (per a, rows b > a) and the
   // contractions of a batch into the packed parts We[i][(a<b)][c] and Wm[i][a][(b<c)]
   {
